@@ -1,0 +1,381 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage it follows. None of them calls the GPU path.
+"""
+import itertools
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import lbinputs as li
+from oracle import analytic as an
+from oracle import exact
+from oracle.oracle import (PSI_EXP, PSI_RHO, SINK_FACES, SINK_NONE, SINK_SPHERE, SINK_ZMAX, Oracle,
+                           OracleParams, feq, lattice_tables)
+
+
+# ---------------------------------------------------------------------------
+# Lattice and equilibrium (Sec. II A, Eq. (eqdis)): exact identities.
+# ---------------------------------------------------------------------------
+
+def test_d3q19_tables_exact_isotropy():
+    ex, ey, ez, w, opp = lattice_tables()
+    e = np.stack([ex, ey, ez], axis=1)
+    W = [Fraction(x).limit_denominator(100) for x in w]
+    assert W[0] == Fraction(1, 3) and all(x == Fraction(1, 18) for x in W[1:7])
+    assert all(x == Fraction(1, 36) for x in W[7:])
+    assert sum(W) == 1
+    assert len({tuple(v) for v in e}) == 19
+    for a in range(3):
+        assert sum(W[i] * int(e[i, a]) for i in range(19)) == 0
+        for b in range(3):
+            s2 = sum(W[i] * int(e[i, a]) * int(e[i, b]) for i in range(19))
+            assert s2 == (Fraction(1, 3) if a == b else 0)
+            for c in range(3):
+                assert sum(W[i] * int(e[i, a] * e[i, b] * e[i, c]) for i in range(19)) == 0
+    # fourth-order isotropy: sum w e_a e_b e_c e_d = (d_ab d_cd + d_ac d_bd + d_ad d_bc)/9
+    for a, b, c, d in itertools.product(range(3), repeat=4):
+        s4 = sum(W[i] * int(e[i, a] * e[i, b] * e[i, c] * e[i, d]) for i in range(19))
+        iso = Fraction((a == b) * (c == d) + (a == c) * (b == d) + (a == d) * (b == c), 9)
+        assert s4 == iso
+    for i in range(19):
+        assert np.all(e[opp[i]] == -e[i]) and opp[opp[i]] == i
+
+
+def test_equilibrium_moments_closed_form():
+    ex, ey, ez, w, opp = lattice_tables()
+    e = np.stack([ex, ey, ez], axis=1).astype(float)
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        rho = rng.uniform(0.01, 1.0)
+        u = rng.uniform(-0.1, 0.1, 3)
+        f = feq(rho, u)
+        assert abs(f.sum() - rho) < 1e-15
+        assert np.allclose(f @ e, rho * u, atol=1e-16, rtol=0)
+        P = (f[:, None, None] * e[:, :, None] * e[:, None, :]).sum(0)
+        assert np.allclose(P, rho * (np.eye(3) / 3 + np.outer(u, u)), atol=1e-15, rtol=0)
+
+
+# ---------------------------------------------------------------------------
+# Special cases and invariants of the whole step.
+# ---------------------------------------------------------------------------
+
+def _params(nx, ny, nz, **kw):
+    return OracleParams(nx, ny, nz, **kw)
+
+
+@pytest.mark.parametrize("psi,g", [(PSI_RHO, 0.9), (PSI_EXP, 3.6)])
+def test_uniform_rest_and_uniform_flow_are_fixed_points(psi, g):
+    o = Oracle(_params(4, 3, 5, g=g, psi=psi))
+    n = o.n
+    u0 = np.array([0.03, -0.02, 0.01])
+    f = np.zeros((2, 19, n))
+    f[0] = feq(0.3, u0)[:, None]
+    f[1] = feq(0.5, u0)[:, None]
+    o.init_from_populations(f)
+    o.step(10)
+    out = o.populations().reshape(2, 19, n)
+    assert np.max(np.abs(out - f)) < 1e-15
+    # the Shan-Chen force of a uniform state vanishes (sum_i w_i e_i = 0)
+    assert np.max(np.abs(o.total_force())) < 1e-13
+
+
+@pytest.mark.parametrize("psi", [PSI_RHO, PSI_EXP])
+def test_mass_and_momentum_conserved_periodic(psi):
+    o = Oracle(_params(5, 4, 6, g=1.3, psi=psi))
+    f = li.random_populations(5, 4, 6, seed=11)
+    o.init_from_populations(f)
+    d0 = o.diagnostics()
+    o.step(40)
+    d1 = o.diagnostics()
+    for c in range(2):
+        assert abs(d1["mass"][c] - d0["mass"][c]) <= 1e-13 * d0["mass"][c]
+    # sum_x sum_c F^c = 0 for symmetric g, so total momentum is conserved
+    assert np.max(np.abs(o.total_force())) < 1e-13
+    assert np.max(np.abs(np.array(d1["momentum"]) - np.array(d0["momentum"]))) < 1e-13
+
+
+@pytest.mark.parametrize("sink,wall,extra", [(SINK_ZMAX, True, {}), (SINK_FACES, False, {}),
+                                             (SINK_SPHERE, False, {"sink_radius": 2.6})])
+def test_sink_conserves_total_mass_and_books_evaporation(sink, wall, extra):
+    """Sec. II C: the partner reset keeps each sink node's total density, so
+    M^A + M^B is constant, and the mass of A removed equals E."""
+    o = Oracle(_params(6, 6, 6, g=0.9, wall_z=wall, sink=sink, rho_h=0.02, **extra))
+    a, b = li.droplet(6, 6, 6, 1.8)
+    o.init_from_density(a, b)
+    d0 = o.diagnostics()
+    assert d0["evaporated"] == 0.0
+    o.step(60)
+    d1 = o.diagnostics()
+    tot0 = d0["mass"][0] + d0["mass"][1]
+    assert abs(d1["mass"][0] + d1["mass"][1] - tot0) <= 1e-13 * tot0
+    assert abs(d1["mass"][0] + d1["evaporated"] - d0["mass"][0]) <= 1e-13 * tot0
+    assert d1["evaporated"] > 0.0  # rho_H below the vapour density: evaporation
+
+
+def test_sink_node_state_is_rest_equilibrium():
+    o = Oracle(_params(4, 4, 8, g=0.9, wall_z=True, sink=SINK_ZMAX, rho_h=0.03))
+    o.init_from_populations(li.random_populations(4, 4, 8, seed=5))
+    o.step(3)
+    f = o.populations()
+    top = f[:, :, 7]
+    fa = feq(0.03, (0, 0, 0))
+    assert np.max(np.abs(top[0] - fa[:, None, None])) < 1e-17
+    rb = top[1].sum(0)
+    assert np.max(np.abs(top[1] - np.array(feq(1.0, (0, 0, 0)))[:, None, None] * rb[None])) < 1e-15
+
+
+def _reflect(f, axis):
+    """Mirror populations in one axis: node and direction components flip."""
+    ex, ey, ez, w, opp = lattice_tables()
+    e = np.stack([ex, ey, ez], axis=1)
+    flip = e.copy()
+    flip[:, axis] *= -1
+    perm = [int(np.where((e == flip[i]).all(1))[0][0]) for i in range(19)]
+    out = np.empty_like(f)
+    sp_axis = {0: 3, 1: 2, 2: 1}[axis]  # axes of f[:, i]: (c, z, y, x)
+    for i in range(19):
+        out[:, perm[i]] = np.flip(f[:, i], axis=sp_axis)
+    return out
+
+
+@pytest.mark.parametrize("axis,sink,wall", [(0, SINK_ZMAX, True), (1, SINK_FACES, False), (2, SINK_FACES, False),
+                                            (2, SINK_NONE, False)])
+def test_mirror_symmetry(axis, sink, wall):
+    """A mirrored initial state evolves into the mirrored state: catches wrong
+    opposite directions, transposed axes and one-sided stencils."""
+    p = _params(5, 4, 6, g=1.1, psi=PSI_EXP, wall_z=wall, sink=sink, rho_h=0.05)
+    f0 = li.random_populations(5, 4, 6, seed=21)
+    o1 = Oracle(p); o1.init_from_populations(f0); o1.step(7)
+    o2 = Oracle(p); o2.init_from_populations(_reflect(f0, axis)); o2.step(7)
+    assert np.max(np.abs(_reflect(o1.populations(), axis) - o2.populations())) < 1e-15
+
+
+def test_component_exchange_symmetry():
+    """Without a sink and with equal tau, swapping A and B commutes with a step."""
+    p = _params(4, 5, 3, g=2.0, psi=PSI_EXP)
+    f0 = li.random_populations(4, 5, 3, seed=8, base_a=0.2, base_b=0.6)
+    o1 = Oracle(p); o1.init_from_populations(f0); o1.step(5)
+    o2 = Oracle(p); o2.init_from_populations(f0[::-1].copy()); o2.step(5)
+    assert np.max(np.abs(o1.populations()[::-1] - o2.populations())) < 1e-15
+
+
+def test_planar_state_independent_of_cross_section():
+    """A z-only state on 1x1xN and 3x2xN gives the same profiles."""
+    a, b = li.film(1, 1, 24, 10)
+    o1 = Oracle(_params(1, 1, 24, g=3.6, psi=PSI_EXP, wall_z=True, sink=SINK_ZMAX, rho_h=0.02))
+    o1.init_from_density(a, b); o1.step(30)
+    a3, b3 = li.film(3, 2, 24, 10)
+    o3 = Oracle(_params(3, 2, 24, g=3.6, psi=PSI_EXP, wall_z=True, sink=SINK_ZMAX, rho_h=0.02))
+    o3.init_from_density(a3, b3); o3.step(30)
+    r1 = o1.density()[0][:, 0, 0]
+    r3 = o3.density()[0]
+    assert np.max(np.abs(r3 - r1[:, None, None])) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Brute force in 40-digit arithmetic on tiny lattices.
+# ---------------------------------------------------------------------------
+
+def _to_exact_pops(f, nx, ny, nz):
+    ex, ey, ez, w, opp = lattice_tables()
+    pops = [dict(), dict()]
+    for c in range(2):
+        for z in range(nz):
+            for y in range(ny):
+                for x in range(nx):
+                    pops[c][(x, y, z)] = {(int(ex[i]), int(ey[i]), int(ez[i])): float(f[c, i, z, y, x])
+                                          for i in range(19)}
+    return pops
+
+
+def _from_exact(lat, nx, ny, nz):
+    ex, ey, ez, w, opp = lattice_tables()
+    out = np.zeros((2, 19, nz, ny, nx))
+    for c in range(2):
+        for (x, y, z), d in lat.f[c].items():
+            for i in range(19):
+                out[c, i, z, y, x] = float(d[(int(ex[i]), int(ey[i]), int(ez[i]))])
+    return out
+
+
+@pytest.mark.parametrize("case", ["wall_zmax_rho", "periodic_exp", "unequal_tau", "sphere_rho"])
+def test_oracle_matches_exact_bruteforce(case):
+    nx, ny, nz = 3, 2, 4
+    kw = dict(g=0.9, psi=PSI_RHO, tau=(1.0, 1.0))
+    ekw = dict(g="0.9", psi_kind="rho")
+    steps = 3
+    if case == "wall_zmax_rho":
+        kw.update(wall_z=True, sink=SINK_ZMAX, rho_h=0.03125)
+        ekw.update(wall_z=True, sink=lambda x, y, z: z == nz - 1, rho_h="0.03125")
+    elif case == "periodic_exp":
+        kw.update(g=3.6, psi=PSI_EXP)
+        ekw.update(g="3.6", psi_kind="exp")
+        steps = 2
+    elif case == "unequal_tau":
+        kw.update(tau=(0.75, 1.25))
+        ekw.update(tau=("0.75", "1.25"))
+    elif case == "sphere_rho":
+        nx, ny, nz = 3, 3, 3
+        kw.update(sink=SINK_SPHERE, sink_radius=1.2, rho_h=0.0625)
+        ekw.update(sink=lambda x, y, z: (x - 1) ** 2 + (y - 1) ** 2 + (z - 1) ** 2 >= 1.44, rho_h="0.0625")
+    f0 = li.random_populations(nx, ny, nz, seed=99, base_a=0.25, base_b=0.5, amp=0.05)
+    o = Oracle(_params(nx, ny, nz, **kw))
+    o.init_from_populations(f0)
+    lat = exact.ExactLattice(nx, ny, nz, **ekw)
+    lat.set_populations(_to_exact_pops(f0, nx, ny, nz))
+    for _ in range(steps):
+        o.step(1)
+        lat.step()
+    ref = _from_exact(lat, nx, ny, nz)
+    got = o.populations()
+    assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
+    assert abs(o.diagnostics()["evaporated"] - float(lat.evaporated)) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Fick's law with the analytic coefficient (Sec. III A).
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mean,g,psi,tau", [
+    (0.37, 0.9, "rho", 1.0),    # the configs' fluid at the symmetric composition
+    (0.30, 1.2, "exp", 1.0),    # psi = 1 - exp(-rho)
+    (0.35, 0.0, "rho", 0.8),    # ideal mixing: D = c_s^2 (tau - 1/2)
+])
+def test_sinusoid_decays_with_paper_diffusion_coefficient(mean, g, psi, tau):
+    """A composition wave decays as exp(-D k^2 t) with D of the small-gradient
+    formula. At a symmetric composition the paper's assumption
+    grad rho^B = -grad rho^A holds exactly, so the match is tight."""
+    nz = 128
+    o = Oracle(_params(1, 1, nz, g=g, psi=PSI_RHO if psi == "rho" else PSI_EXP, tau=(tau, tau)))
+    a, b = li.sinus(1, 1, nz, mean, mean, 1e-5)
+    o.init_from_density(a, b)
+    s = np.sin(2 * np.pi * np.arange(nz) / nz)
+    amps, ts = [], []
+    for k in range(9):
+        if k:
+            o.step(500)
+        ra, _ = o.density()
+        amps.append((ra[:, 0, 0] - mean) @ s / (s @ s))
+        ts.append(500 * k)
+    slope = np.polyfit(ts[2:], np.log(amps[2:]), 1)[0]
+    d_meas = -slope / (2 * np.pi / nz) ** 2
+    d_paper = an.diffusion_small_gradient(mean, mean, g, psi, tau)
+    assert abs(d_meas / d_paper - 1) < 0.01, (d_meas, d_paper)
+
+
+# ---------------------------------------------------------------------------
+# Planar film (Sec. III B): coexistence and the sqrt(t) law.
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def equilibrated_film64():
+    nz = 64
+    o = Oracle(_params(1, 1, nz, g=3.6, psi=PSI_EXP, wall_z=True))
+    a, b = li.film(1, 1, nz, nz // 2)
+    o.init_from_density(a, b)
+    o.step(40000)
+    return o.populations().copy()
+
+
+def test_film_coexistence_matches_printed_values():
+    """Sec. III B: after equilibration rho_ma ~ 0.704, rho_mi ~ 0.036 and an
+    interface about 5 nodes wide (psi = 1 - exp(-rho), g = 3.6, tau = 1)."""
+    nz = 128
+    o = Oracle(_params(1, 1, nz, g=3.6, psi=PSI_EXP, wall_z=True))
+    a, b = li.film(1, 1, nz, 64)
+    o.init_from_density(a, b)
+    o.step(60000)
+    ra = o.density()[0][:, 0, 0]
+    rho_ma, rho_mi = ra[20:44].mean(), ra[84:108].mean()
+    assert abs(rho_mi - 0.036) < 0.001, rho_mi
+    assert abs(rho_ma - 0.704) < 0.006, rho_ma
+    lo, hi = rho_mi + 0.1 * (rho_ma - rho_mi), rho_ma - 0.1 * (rho_ma - rho_mi)
+    zc = np.arange(nz, dtype=float)
+    up = np.interp(hi, ra[70:50:-1], zc[70:50:-1])
+    dn = np.interp(lo, ra[70:50:-1], zc[70:50:-1])
+    assert 2.5 < dn - up < 7.0, dn - up
+
+
+def _run_film(f0, rho_h, total):
+    nz = 64
+    o = Oracle(_params(1, 1, nz, g=3.6, psi=PSI_EXP, wall_z=True))
+    o.init_from_populations(f0)
+    ra, rb = o.density()
+    rho_ma, rho_mi, rho_t = ra[5, 0, 0], ra[nz - 5, 0, 0], ra[nz - 5, 0, 0] + rb[nz - 5, 0, 0]
+    o.set_sink(SINK_ZMAX, rho_h, 0.0)
+    ts, xs = [], []
+    for k in range(40):
+        o.step(total // 40)
+        ts.append((k + 1) * (total // 40))
+        xs.append(o.diagnostics()["z_interface"])
+    return np.array(ts), np.array(xs), rho_ma, rho_mi, rho_t
+
+
+def test_film_interface_follows_sqrt_t_law(equilibrated_film64):
+    """Eq. (xt), sign-fixed: (x_H - d0 - x_I)^2 grows linearly in t with slope
+    2K, K = D (rho_mi - rho_H)/(rho_ma - rho_mi/2 - rho_H/2), D at the mean
+    vapour composition. Only the quasi-static part (t > T/4) is fitted."""
+    T = 100000
+    slopes = {}
+    for rho_h in (0.02, 0.03):
+        ts, xs, rho_ma, rho_mi, rho_t = _run_film(equilibrated_film64, rho_h, T)
+        assert np.all(np.diff(xs) < 0)  # rho_H < rho_mi: the film evaporates
+        y = (63 - xs) ** 2
+        sel = ts > T / 4
+        p, res, *_ = np.polyfit(ts[sel], y[sel], 1, full=True)
+        r2 = 1 - res[0] / np.sum((y[sel] - y[sel].mean()) ** 2)
+        assert r2 > 0.999, r2
+        ram = 0.5 * (rho_mi + rho_h)
+        D = an.diffusion_small_gradient(ram, rho_t - ram, 3.6, "exp")
+        K = an.film_rate_constant(D, rho_ma, rho_mi, rho_h)
+        assert abs(p[0] / (2 * K) - 1) < 0.10, (rho_h, p[0], 2 * K)
+        slopes[rho_h] = (p[0], K)
+    # the evaporation rate scales with rho_mi - rho_H (Sec. III B)
+    ratio_meas = slopes[0.02][0] / slopes[0.03][0]
+    ratio_law = slopes[0.02][1] / slopes[0.03][1]
+    assert abs(ratio_meas / ratio_law - 1) < 0.05, (ratio_meas, ratio_law)
+
+
+def test_condensation_when_rho_h_above_minority(equilibrated_film64):
+    """Sec. II C: rho_H above the minority density makes the film grow."""
+    ts, xs, *_ = _run_film(equilibrated_film64, 0.05, 8000)
+    assert xs[-1] > xs[0] + 0.05
+
+
+# ---------------------------------------------------------------------------
+# Droplet closed forms (Sec. III C): transcription checks of the readings.
+# ---------------------------------------------------------------------------
+
+def test_droplet_mass_derivative_matches_mass_integral():
+    """Eq. (mass-df2) is d/dR of Eq. (drop-mass-1)."""
+    RH, d0, rma, rmi, rh = 60.0, 2.5, 0.712, 0.037, 0.02
+    for R in (12.0, 25.0, 40.0):
+        h = 1e-3
+        fd = (an.droplet_mass(R + h, RH, d0, rma, rmi, rh) - an.droplet_mass(R - h, RH, d0, rma, rmi, rh)) / (2 * h)
+        assert abs(fd / an.droplet_dMdR(R, RH, d0, rma, rmi, rh) - 1) < 1e-4
+
+
+def test_laplace_mass_derivative_is_total_derivative():
+    """Eq. (drop-mass-df4) with d read as d0 is the total d/dR of Eq.
+    (drop-mass-1) after substituting Eqs. (rho_ma) and (rho_mi)."""
+    RH, d0, R0, gamma, rma0, rmi0, rh = 60.0, 2.5, 40.0, 0.01, 0.712, 0.037, 0.02
+
+    def mass(R):
+        rma, rmi = an.laplace_densities(R, R0, gamma, rma0, rmi0)
+        return an.droplet_mass(R, RH, d0, rma, rmi, rh)
+
+    for R in (10.0, 20.0, 35.0):
+        h = 1e-3
+        fd = (mass(R + h) - mass(R - h)) / (2 * h)
+        assert abs(fd / an.droplet_dMdR_laplace(R, RH, d0, R0, gamma, rma0, rmi0, rh) - 1) < 1e-4
+
+
+def test_rk4_reproduces_film_closed_form():
+    """RK4 on the sign-fixed Eq. (xit) reproduces Eq. (xt)."""
+    K, xh, d0, x0 = 3e-3, 127.0, 2.5, 64.0
+    ts, ys = an.rk4(lambda x: -K / (xh - x - d0), x0, 2e5, 500.0)
+    for t, y in zip(ts[::50], ys[::50]):
+        assert abs(y - an.film_interface(t, x0, xh, d0, K)) < 1e-8
