@@ -1,0 +1,192 @@
+/*
+ * lbsc: two-component D3Q19 Shan-Chen lattice Boltzmann step with the
+ * mass-conserving evaporation sink, for AMD MI355X (gfx950).
+ *
+ * Method: Hessling, Xie and Harting, "Diffusion dominated evaporation in
+ * multicomponent lattice Boltzmann simulations", arXiv:1701.03637, Sec. II:
+ *   - BGK update per component, Eq. (LBM), towards the second-order
+ *     equilibrium of Eq. (eqdis) on D3Q19 (w = 1/3, 1/18, 1/36, c_s^2 = 1/3);
+ *   - densities and velocities as defined after Eq. (eqdis), with the common
+ *     velocity u' = sum_c rho^c u^c / sum_c rho^c;
+ *   - Shan-Chen inter-component force, Eq. (sc), with psi of Eq. (psifunc)
+ *     (psi = 1 - exp(-rho), rho_0 = 1) or psi = rho, applied as the velocity
+ *     shift tau^c F^c / rho^c (Sec. II B);
+ *   - periodic boundaries, optionally a bounce-back wall on the z seam
+ *     (Sec. II A);
+ *   - the evaporation sink of Sec. II C: at sink nodes component A (the
+ *     evaporating one) is reset to f^eq(rho_H, 0) and component B to
+ *     f^eq(rhoA + rhoB - rho_H, 0), from the densities streamed in during the
+ *     step, so every sink node keeps its total density; sink nodes neither
+ *     collide nor feel the force.
+ *
+ * Conventions
+ *   - Every call returns an lbsc_status; nothing throws across this ABI. On
+ *     failure lbsc_last_error(ctx) returns a message for that context.
+ *   - The caller owns all device memory: it allocates the two population
+ *     buffers and the scratch buffer (sizes from lbsc_required_bytes, every
+ *     pointer 256-byte aligned) and hands them over with lbsc_bind. The
+ *     library never allocates or frees device memory; it owns only host
+ *     metadata, one private capture stream and HIP graph objects.
+ *   - Work is enqueued asynchronously on the stream set by lbsc_set_stream
+ *     (default: the null stream). Calls that return host data
+ *     (lbsc_diagnostics, lbsc_load) and calls that change the instance table
+ *     (lbsc_bind, lbsc_init_*, lbsc_set_sink, lbsc_set_tiles, lbsc_tune,
+ *     lbsc_step's first step after an init or sink change) synchronise that
+ *     stream.
+ *   - A context must not be used from two host threads at once.
+ *   - A context holds one or more instances (independent lattices with their
+ *     own size and fluid parameters) that are stepped together in one launch
+ *     per time step. Instance indices run from 0 to n_inst - 1.
+ *   - Node order everywhere is z-major: node = (z*ny + y)*nx + x.
+ *   - Component 0 is A (held at rho_H by the sink), component 1 is B.
+ *   - Direction order: 0 rest, 1..6 = +x,-x,+y,-y,+z,-z, 7..18 = the face
+ *     diagonals (+1,+1,0),(-1,-1,0),(+1,-1,0),(-1,+1,0),(+1,0,+1),(-1,0,-1),
+ *     (+1,0,-1),(-1,0,+1),(0,+1,+1),(0,-1,-1),(0,+1,-1),(0,-1,+1).
+ */
+#ifndef LBSC_H
+#define LBSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lbsc_status {
+    LBSC_OK = 0,
+    LBSC_E_ARG = -1,         /* invalid argument, size or pointer */
+    LBSC_E_STATE = -2,       /* call not valid in the context's state (e.g. unbound) */
+    LBSC_E_HIP = -3,         /* a HIP runtime call failed */
+    LBSC_E_NONFINITE = -4,   /* diagnostics found a non-finite density */
+    LBSC_E_UNSUPPORTED = -5  /* option not supported */
+} lbsc_status;
+
+/* Storage precision of the populations. FP32S/FP16S store the deviation
+ * f - w_i*shift[c] and compute in FP32; FP64 stores f and computes in FP64.
+ * Global sums (mass, evaporated mass, interface) are FP64 in every form. */
+enum { LBSC_FP64 = 0, LBSC_FP32S = 1, LBSC_FP16S = 2 };
+enum { LBSC_PSI_RHO = 0, LBSC_PSI_EXP = 1 };
+/* Sink node sets: the plane z = nz-1; the six faces; all nodes at distance
+ * >= sink_radius from center. */
+enum { LBSC_SINK_NONE = 0, LBSC_SINK_ZMAX = 1, LBSC_SINK_FACES = 2, LBSC_SINK_SPHERE = 3 };
+
+typedef struct lbsc_params {
+    int32_t nx, ny, nz;      /* lattice size, each 1..4096, nx*ny*nz < 2^31 */
+    int32_t wall_z;          /* 1: half-way bounce-back wall on the z seam */
+    double tau[2];           /* relaxation times tau^A, tau^B (> 0.5) */
+    double g;                /* interaction strength g^{AB} = g^{BA} */
+    int32_t psi;             /* LBSC_PSI_RHO or LBSC_PSI_EXP */
+    int32_t precision;       /* LBSC_FP64/FP32S/FP16S; equal for all instances */
+    double shift[2];         /* rho0^c of shifted storage (ignored for FP64) */
+    int32_t sink;            /* LBSC_SINK_* */
+    int32_t reserved;
+    double rho_h;            /* density imposed on A at sink nodes */
+    double sink_radius;      /* LBSC_SINK_SPHERE only */
+    double center[3];        /* sphere centre (x, y, z) in node units */
+    double phi_delta[2];     /* rhoA - rhoB inside / outside a droplet, for the
+                                volume-fraction radius diagnostic */
+} lbsc_params;
+
+typedef struct lbsc_diag {
+    int64_t step;            /* time steps taken since the last init */
+    double mass[2];          /* sum over nodes of rho^A, rho^B */
+    double evaporated;       /* mass of A removed by the sink since init */
+    double evap_rate;        /* sum over sink nodes of (rhoA_pre - rho_H) in the
+                                reset that formed the current state */
+    double momentum[3];      /* sum over nodes and components of j^c */
+    double z_interface;      /* first zero of the plane mean of rhoA - rhoB,
+                                scanning up from z = 0, linearly interpolated;
+                                NaN if none */
+    double r_droplet;        /* (3 V / 4 pi)^(1/3), V = sum of the clamped
+                                volume fraction of A */
+    int64_t nonfinite;       /* nodes with a non-finite density */
+    int64_t nonpositive;     /* nodes with a density <= 0 */
+} lbsc_diag;
+
+typedef struct lbsc_ctx lbsc_ctx;
+
+/* Tile schedule of the fused step kernel: nt threads per block (256 or 512),
+ * xy tile tw x th (tw, th <= 128, tw*th <= nt), z chunk of nzc planes. Zero
+ * or negative fields mean "choose automatically". */
+typedef struct lbsc_tiles {
+    int32_t nt, tw, th, nzc;
+} lbsc_tiles;
+
+/* Static description of a status code. */
+const char* lbsc_status_string(lbsc_status s);
+/* Message of the last failure on ctx ("" if none). */
+const char* lbsc_last_error(const lbsc_ctx* ctx);
+/* Library version string. */
+const char* lbsc_version(void);
+
+/* Creates a context of n_inst instances (params[0..n_inst-1]). Validates
+ * sizes and parameters; no device memory is touched. */
+lbsc_status lbsc_create(int32_t n_inst, const lbsc_params* params, lbsc_ctx** out);
+/* Releases host metadata and graphs; never frees the caller's buffers. */
+lbsc_status lbsc_destroy(lbsc_ctx* ctx);
+
+/* Bytes the caller must allocate: each of the two population buffers, and the
+ * scratch buffer (instance table, work items, FP64 accumulators). */
+lbsc_status lbsc_required_bytes(const lbsc_ctx* ctx, size_t* pop_bytes, size_t* scratch_bytes);
+/* Binds caller-owned device buffers (borrowed until lbsc_destroy). Clears the
+ * evaporation accumulators and uploads the instance table. */
+lbsc_status lbsc_bind(lbsc_ctx* ctx, void* pop0, void* pop1, void* scratch);
+/* Stream for all following work (a hipStream_t; NULL = null stream). */
+lbsc_status lbsc_set_stream(lbsc_ctx* ctx, void* hip_stream);
+
+/* Initial state f = f^eq(rho, 0) of instance inst from two FP64 device arrays
+ * of nx*ny*nz densities, then the initial sink reset, which is not counted as
+ * evaporated mass. Resets the step counter and the evaporated mass. */
+lbsc_status lbsc_init_from_density(lbsc_ctx* ctx, int32_t inst, const double* rhoA_dev, const double* rhoB_dev);
+/* As above from full FP64 device populations f[(c*19 + i)*n + node]. */
+lbsc_status lbsc_init_from_populations(lbsc_ctx* ctx, int32_t inst, const double* f_dev);
+
+/* Changes the sink of instance inst (kind, rho_H, sphere radius). Its nodes
+ * skip the next collision; they are reset at the end of that step. */
+lbsc_status lbsc_set_sink(lbsc_ctx* ctx, int32_t inst, int32_t kind, double rho_h, double radius);
+
+/* Advances every instance by n time steps. */
+lbsc_status lbsc_step(lbsc_ctx* ctx, int64_t n);
+/* Replays steady-state steps as HIP graphs of `steps` launches (even, >= 2);
+ * 0 switches graphs off. */
+lbsc_status lbsc_set_graph(lbsc_ctx* ctx, int32_t steps);
+/* Sets the tile schedule (see lbsc_tiles). */
+lbsc_status lbsc_set_tiles(lbsc_ctx* ctx, const lbsc_tiles* tiles);
+/* Times candidate tile schedules for `steps` steps each and keeps the
+ * fastest; writes it to *chosen if non-NULL. The populations advance during
+ * tuning, so call it before lbsc_init_*. */
+lbsc_status lbsc_tune(lbsc_ctx* ctx, int32_t steps, lbsc_tiles* chosen);
+/* Number of work items (blocks per step) of the current schedule. */
+lbsc_status lbsc_num_items(const lbsc_ctx* ctx, int32_t* n_items);
+
+/* FP64 read-outs of the state S(t) (post-stream, post-sink) of instance inst
+ * into caller device arrays: densities of component comp (n values); the
+ * densities of both components and the barycentric velocity U of Eq. (velw)
+ * (out_u[d*n + node], d = x, y, z; any of the three pointers may be NULL
+ * except that U needs both density arrays); all populations f[(c*19+i)*n +
+ * node]. */
+lbsc_status lbsc_read_density(lbsc_ctx* ctx, int32_t inst, int32_t comp, double* out_dev);
+lbsc_status lbsc_read_observables(lbsc_ctx* ctx, int32_t inst, double* rhoA_dev, double* rhoB_dev, double* u_dev);
+lbsc_status lbsc_read_populations(lbsc_ctx* ctx, int32_t inst, double* f_dev);
+
+/* FP64 diagnostics of instance inst into a host struct (synchronises).
+ * Returns LBSC_E_NONFINITE (with *out filled) if a density is not finite. */
+lbsc_status lbsc_diagnostics(lbsc_ctx* ctx, int32_t inst, lbsc_diag* out);
+
+/* Checkpoint of the whole context into a caller device buffer of
+ * lbsc_checkpoint_bytes bytes; lbsc_load restores it into a context created
+ * with the same parameters. */
+lbsc_status lbsc_checkpoint_bytes(const lbsc_ctx* ctx, size_t* bytes);
+lbsc_status lbsc_save(lbsc_ctx* ctx, void* blob_dev);
+lbsc_status lbsc_load(lbsc_ctx* ctx, const void* blob_dev);
+
+/* Host-only checks of the index geometry (no GPU needed); 0 on success,
+ * otherwise the number of failed checks. */
+int32_t lbsc_selftest(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBSC_H */

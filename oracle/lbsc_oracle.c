@@ -43,6 +43,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define NQ 19
 
@@ -496,3 +499,13 @@ void orc_diagnostics(orc_lattice *L, orc_diag *out)
 
 double orc_evaporated(const orc_lattice *L) { return L->evaporated; }
 long long orc_step_count(const orc_lattice *L) { return L->step; }
+
+/* Threads the per-node loops use (1 without OpenMP). */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

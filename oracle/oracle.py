@@ -88,6 +88,7 @@ def _load():
         lib.orc_diagnostics.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Diag)]
         lib.orc_lattice_tables.argtypes = [ip, ip, ip, dp, ip]
         lib.orc_feq.argtypes = [ctypes.c_double] * 4 + [dp]
+        lib.orc_num_threads.restype = ctypes.c_int
         _lib = lib
         return lib
 
@@ -103,6 +104,11 @@ def lattice_tables():
     w = (ctypes.c_double * 19)(); opp = (ctypes.c_int * 19)()
     lib.orc_lattice_tables(ex, ey, ez, w, opp)
     return (np.array(ex[:]), np.array(ey[:]), np.array(ez[:]), np.array(w[:]), np.array(opp[:]))
+
+
+def num_threads() -> int:
+    """Threads the oracle's per-node loops use."""
+    return int(_load().orc_num_threads())
 
 
 def feq(rho: float, u) -> np.ndarray:

@@ -1,0 +1,567 @@
+// HIP kernels of the two-component D3Q19 Shan-Chen step with the
+// mass-conserving evaporation sink (Hessling, Xie and Harting,
+// arXiv:1701.03637, Sec. II), written for gfx950 (wave64, no MFMA: the step
+// is a memory-bound stencil, not a contraction).
+//
+// Storage. The populations of one instance live in an SoA arena:
+//   arena[base + (c*19 + i)*pstride + node],  node = (z*ny + y)*nx + x.
+// The stored buffer holds post-collision populations f*(t-1); the state S(t)
+// of the method (post-stream, post-sink) is obtained by pulling,
+//   f_i(x) = f*_i(x - e_i), or f*_opp(i)(x) across a z-seam wall,
+// followed by the sink reset of the sink that was active when S(t) formed.
+// Shifted storage keeps delta = f - w_i*rho0^c (rho0 = 0 for plain FP64);
+// arithmetic is FP64 for FP64 storage and FP32 otherwise.
+//
+// Fused step (one launch per time step): a block owns an xy tile and marches
+// along z with a three-plane ring of psi (tile plus a one-node halo) in LDS.
+// Each tile node is pulled once per step into registers; halo nodes are
+// pulled only to form their density. Collision reads the 18 neighbour psi
+// values from LDS and writes f* aligned to the other buffer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lattice.h"
+
+namespace lbsc {
+
+template <typename T> struct Arith { using A = float; };
+template <> struct Arith<double> { using A = double; };
+
+template <typename A> __device__ __forceinline__ A psi_of(A rho, int psi_exp);
+template <> __device__ __forceinline__ double psi_of<double>(double rho, int psi_exp)
+{
+    return psi_exp ? 1.0 - exp(-rho) : rho;
+}
+template <> __device__ __forceinline__ float psi_of<float>(float rho, int psi_exp)
+{
+    return psi_exp ? -expm1f(-rho) : rho;
+}
+
+// ---------------------------------------------------------------------------
+// Pull of one node: 2 x 19 populations (delta form) and the sink reset.
+// ---------------------------------------------------------------------------
+
+template <typename T, typename A>
+struct NodeVals {
+    A f[2][kQ];
+    A rho[2];
+};
+
+template <typename T, typename A>
+__device__ __forceinline__ void pull_node(const T* __restrict__ src, const Inst& I, int x, int y, int z,
+                                          NodeVals<T, A>& v)
+{
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        PullSrc s = pull_src(i, x, y, z, I.nx, I.ny, I.nz, I.wall_z);
+        const int q = s.reflected ? opp(i) : i;
+        const int64_t node = node_of(s.x, s.y, s.z, I.nx, I.ny);
+        v.f[0][i] = (A)src[(int64_t)q * I.pstride + node];
+        v.f[1][i] = (A)src[(int64_t)(kQ + q) * I.pstride + node];
+    }
+}
+
+template <typename T, typename A>
+__device__ __forceinline__ void node_density(const Inst& I, NodeVals<T, A>& v)
+{
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        A r = (A)I.shift[c];
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) r += v.f[c][i];
+        v.rho[c] = r;
+    }
+}
+
+// Sink reset (Sec. II C): A -> f^eq(rho_H, 0), B -> f^eq(rhoA + rhoB - rho_H, 0)
+// from the densities pulled in this step. Returns rhoA_pre - rho_H in FP64.
+template <typename T, typename A>
+__device__ __forceinline__ double sink_reset(const Inst& I, NodeVals<T, A>& v)
+{
+    const double rho_h = I.reset.rho_h;
+    const double flux = (double)v.rho[0] - rho_h;
+    const A rbh = v.rho[0] + v.rho[1] - (A)rho_h;
+    const A da = (A)(rho_h - I.shift[0]);
+    const A db = rbh - (A)I.shift[1];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        v.f[0][i] = (A)wgt(i) * da;
+        v.f[1][i] = (A)wgt(i) * db;
+    }
+    node_density<T, A>(I, v);
+    return flux;
+}
+
+// ---------------------------------------------------------------------------
+// Collision of one fluid node (Eqs. (LBM), (eqdis), (sc); Sec. II B shift).
+// S[c] = sum_{i>0} w_i psi^{cbar}(x + e_i) e_i, the neighbour sum of Eq. (sc).
+// ---------------------------------------------------------------------------
+
+template <typename T, typename A>
+__device__ __forceinline__ void collide_node(const Inst& I, NodeVals<T, A>& v, const A S[2][3], A psiA, A psiB)
+{
+    A j[2][3];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        A jx = 0, jy = 0, jz = 0;
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            if (ex(i)) jx += ex(i) > 0 ? v.f[c][i] : -v.f[c][i];
+            if (ey(i)) jy += ey(i) > 0 ? v.f[c][i] : -v.f[c][i];
+            if (ez(i)) jz += ez(i) > 0 ? v.f[c][i] : -v.f[c][i];
+        }
+        j[c][0] = jx; j[c][1] = jy; j[c][2] = jz;
+    }
+    const A rt = v.rho[0] + v.rho[1];
+    const A up[3] = {(j[0][0] + j[1][0]) / rt, (j[0][1] + j[1][1]) / rt, (j[0][2] + j[1][2]) / rt};
+    const A psi[2] = {psiA, psiB};
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const A tau = (A)I.tau[c];
+        const A g = (A)I.g;
+        A u[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const A F = -psi[c] * g * S[c][d];
+            u[d] = up[d] + (v.rho[c] != (A)0 ? tau * F / v.rho[c] : (A)0);
+        }
+        const A uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        const A rho = v.rho[c];
+        const A drho = rho - (A)I.shift[c];
+        const A omega = (A)1 / tau;
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            const A eu = (A)ex(i) * u[0] + (A)ey(i) * u[1] + (A)ez(i) * u[2];
+            const A q = (A)3 * eu + (A)4.5 * eu * eu - (A)1.5 * uu;
+            const A feq = (A)wgt(i) * (drho + rho * q);
+            v.f[c][i] = v.f[c][i] - (v.f[c][i] - feq) * omega;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The fused step kernel.
+// ---------------------------------------------------------------------------
+
+template <int NT> struct Foot {
+    // Largest (tw + 2)(th + 2) over tiles with tw * th <= NT, tw, th <= 128.
+    static constexpr int kMax = NT + 2 * (128 + 128) + 4;
+};
+
+__device__ __forceinline__ void ring_coord(int r, int tw, int th, int& fx, int& fy)
+{
+    const int row = tw + 2;
+    if (r < row) { fx = r - 1; fy = -1; return; }
+    r -= row;
+    if (r < row) { fx = r - 1; fy = th; return; }
+    r -= row;
+    if (r < th) { fx = -1; fy = r; return; }
+    r -= th;
+    fx = tw; fy = r;
+}
+
+__device__ __forceinline__ int xcd_item(int b, int n_items)
+{
+    // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous run of items so neighbouring tiles share its L2.
+    const int per = (n_items + 7) >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+template <typename A>
+__device__ __forceinline__ A block_sum_wave(A v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, const Item* __restrict__ items,
+                                             int n_items, const T* __restrict__ src, T* __restrict__ dst,
+                                             double* __restrict__ eacc)
+{
+    using A = typename Arith<T>::A;
+    constexpr int FP = Foot<NT>::kMax;
+    __shared__ A psiS[3][2][FP];
+    __shared__ double red[NT / 64];
+
+    const int k = xcd_item(blockIdx.x, n_items);
+    if (k >= n_items) return;
+    const Item it = items[k];
+    const Inst I = insts[it.inst];
+    const T* __restrict__ s = src + I.base;
+    T* __restrict__ d = dst + I.base;
+
+    const int t = threadIdx.x;
+    const int tw = it.tw, th = it.th;
+    const int row = tw + 2;
+    const bool own = t < tw * th;
+    const int tx = own ? t % tw : 0;
+    const int ty = own ? t / tw : 0;
+    const int x = wrap(it.x0 + tx, I.nx);
+    const int y = wrap(it.y0 + ty, I.ny);
+    const int nring = 2 * row + 2 * th;
+    const int z0 = it.z0, z1 = it.z0 + it.nzc;
+    const bool book = I.count_reset != 0 && I.reset.kind != kSinkNone;
+    double eflux = 0.0;
+
+    NodeVals<T, A> cur, nxt;
+
+    // Pull plane zq (logical z) into LDS slot sl; tile nodes keep their values.
+    auto load_plane = [&](int zq, int sl, NodeVals<T, A>& keep) {
+        const int zp = psi_plane(zq, I.nz, I.wall_z);
+        if (own) {
+            pull_node<T, A>(s, I, x, y, zp, keep);
+            node_density<T, A>(I, keep);
+            if (in_sink(I.reset, x, y, zp, I.nx, I.ny, I.nz)) {
+                const double fl = sink_reset<T, A>(I, keep);
+                if (book && zq >= z0 && zq < z1) eflux += fl;
+            }
+            const int fi = (ty + 1) * row + tx + 1;
+            psiS[sl][0][fi] = psi_of<A>(keep.rho[0], I.psi_exp);
+            psiS[sl][1][fi] = psi_of<A>(keep.rho[1], I.psi_exp);
+        }
+        for (int r = t; r < nring; r += NT) {
+            int fx, fy;
+            ring_coord(r, tw, th, fx, fy);
+            const int hx = wrap(it.x0 + fx, I.nx), hy = wrap(it.y0 + fy, I.ny);
+            NodeVals<T, A> h;
+            pull_node<T, A>(s, I, hx, hy, zp, h);
+            node_density<T, A>(I, h);
+            if (in_sink(I.reset, hx, hy, zp, I.nx, I.ny, I.nz)) sink_reset<T, A>(I, h);
+            const int fi = (fy + 1) * row + fx + 1;
+            psiS[sl][0][fi] = psi_of<A>(h.rho[0], I.psi_exp);
+            psiS[sl][1][fi] = psi_of<A>(h.rho[1], I.psi_exp);
+        }
+    };
+
+    // Collide plane z of the tile node held in v and store f* to dst.
+    auto collide_plane = [&](int z, NodeVals<T, A>& v) {
+        if (!own) return;
+        const int sm = (z - z0) % 3, s0 = (z - z0 + 1) % 3, sp = (z - z0 + 2) % 3;
+        const int64_t node = node_of(x, y, z, I.nx, I.ny);
+        if (!in_sink(I.cur, x, y, z, I.nx, I.ny, I.nz)) {
+            A S[2][3] = {{0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+            for (int i = 1; i < kQ; ++i) {
+                const int sl = ez(i) < 0 ? sm : (ez(i) > 0 ? sp : s0);
+                const int fi = (ty + 1 + ey(i)) * row + tx + 1 + ex(i);
+                const A w = (A)wgt(i);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const A p = w * psiS[sl][1 - c][fi];
+                    if (ex(i)) S[c][0] += ex(i) > 0 ? p : -p;
+                    if (ey(i)) S[c][1] += ey(i) > 0 ? p : -p;
+                    if (ez(i)) S[c][2] += ez(i) > 0 ? p : -p;
+                }
+            }
+            const int fc = (ty + 1) * row + tx + 1;
+            collide_node<T, A>(I, v, S, psiS[s0][0][fc], psiS[s0][1][fc]);
+        }
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            d[(int64_t)i * I.pstride + node] = (T)v.f[0][i];
+            d[(int64_t)(kQ + i) * I.pstride + node] = (T)v.f[1][i];
+        }
+    };
+
+    load_plane(z0 - 1, 0, nxt);
+    load_plane(z0, 1, cur);
+    for (int z = z0; z < z1; z += 2) {
+        load_plane(z + 1, (z - z0 + 2) % 3, nxt);
+        __syncthreads();
+        collide_plane(z, cur);
+        __syncthreads();
+        if (z + 1 < z1) {
+            load_plane(z + 2, (z - z0 + 3) % 3, cur);
+            __syncthreads();
+            collide_plane(z + 1, nxt);
+            __syncthreads();
+        }
+    }
+
+    if (book) {
+        double e = block_sum_wave(eflux);
+        if ((t & 63) == 0) red[t >> 6] = e;
+        __syncthreads();
+        if (t == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < NT / 64; ++w) sum += red[w];
+            eacc[k] += sum;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation: write the stored buffer so that pulling it yields S(0).
+// The slot P_i(y) is read by y + e_i as population i, or, when y + e_i lies
+// across a z-seam wall, by y itself as population opp(i).
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_init_density(Inst I, const double* __restrict__ rhoA, const double* __restrict__ rhoB,
+                               T* __restrict__ dst)
+{
+    using A = typename Arith<T>::A;
+    const int64_t n = I.n;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(k % I.nx);
+        const int y = (int)((k / I.nx) % I.ny);
+        const int z = (int)(k / ((int64_t)I.nx * I.ny));
+        T* d = dst + I.base;
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            const int zt = z + ez(i);
+            int64_t src;
+            if (I.wall_z && (zt < 0 || zt >= I.nz))
+                src = k;
+            else
+                src = node_of(wrap(x + ex(i), I.nx), wrap(y + ey(i), I.ny), wrap(zt, I.nz), I.nx, I.ny);
+            const double fa = wgt(i) * rhoA[src];
+            const double fb = wgt(i) * rhoB[src];
+            d[(int64_t)i * I.pstride + k] = (T)(A)(fa - wgt(i) * I.shift[0]);
+            d[(int64_t)(kQ + i) * I.pstride + k] = (T)(A)(fb - wgt(i) * I.shift[1]);
+        }
+    }
+}
+
+// From full FP64 populations f[(c*19 + i)*n + node].
+template <typename T>
+__global__ void k_init_pops(Inst I, const double* __restrict__ f, T* __restrict__ dst)
+{
+    using A = typename Arith<T>::A;
+    const int64_t n = I.n;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(k % I.nx);
+        const int y = (int)((k / I.nx) % I.ny);
+        const int z = (int)(k / ((int64_t)I.nx * I.ny));
+        T* d = dst + I.base;
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            const int zt = z + ez(i);
+            int64_t src;
+            int q;
+            if (I.wall_z && (zt < 0 || zt >= I.nz)) {
+                src = k;
+                q = opp(i);
+            } else {
+                src = node_of(wrap(x + ex(i), I.nx), wrap(y + ey(i), I.ny), wrap(zt, I.nz), I.nx, I.ny);
+                q = i;
+            }
+            for (int c = 0; c < 2; ++c)
+                d[(int64_t)(c * kQ + i) * I.pstride + k] =
+                    (T)(A)(f[(int64_t)(c * kQ + q) * n + src] - wgt(i) * I.shift[c]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Read-outs of S(t) in FP64.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ void state_at(const T* s, const Inst& I, int x, int y, int z,
+                                         NodeVals<T, typename Arith<T>::A>& v)
+{
+    using A = typename Arith<T>::A;
+    pull_node<T, A>(s, I, x, y, z, v);
+    node_density<T, A>(I, v);
+    if (in_sink(I.reset, x, y, z, I.nx, I.ny, I.nz)) sink_reset<T, A>(I, v);
+}
+
+template <typename T>
+__global__ void k_read_density(Inst I, const T* __restrict__ src, double* __restrict__ outA,
+                               double* __restrict__ outB)
+{
+    using A = typename Arith<T>::A;
+    const T* s = src + I.base;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < I.n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(k % I.nx), y = (int)((k / I.nx) % I.ny), z = (int)(k / ((int64_t)I.nx * I.ny));
+        NodeVals<T, A> v;
+        state_at<T>(s, I, x, y, z, v);
+        if (outA) outA[k] = (double)v.rho[0];
+        if (outB) outB[k] = (double)v.rho[1];
+    }
+}
+
+template <typename T>
+__global__ void k_read_pops(Inst I, const T* __restrict__ src, double* __restrict__ out)
+{
+    using A = typename Arith<T>::A;
+    const T* s = src + I.base;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < I.n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(k % I.nx), y = (int)((k / I.nx) % I.ny), z = (int)(k / ((int64_t)I.nx * I.ny));
+        NodeVals<T, A> v;
+        state_at<T>(s, I, x, y, z, v);
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int i = 0; i < kQ; ++i)
+                out[(int64_t)(c * kQ + i) * I.n + k] = (double)v.f[c][i] + wgt(i) * I.shift[c];
+    }
+}
+
+// Barycentric velocity U of Eq. (velw) from S(t) and its densities (already
+// written by k_read_density): U = (sum_c j^c + (F^A + F^B)/2) / sum_c rho^c.
+template <typename T>
+__global__ void k_read_velocity(Inst I, const T* __restrict__ src, const double* __restrict__ rhoA,
+                                const double* __restrict__ rhoB, double* __restrict__ U)
+{
+    using A = typename Arith<T>::A;
+    const T* s = src + I.base;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < I.n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(k % I.nx), y = (int)((k / I.nx) % I.ny), z = (int)(k / ((int64_t)I.nx * I.ny));
+        NodeVals<T, A> v;
+        state_at<T>(s, I, x, y, z, v);
+        double num[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                num[0] += (double)v.f[c][i] * ex(i);
+                num[1] += (double)v.f[c][i] * ey(i);
+                num[2] += (double)v.f[c][i] * ez(i);
+            }
+        if (!in_sink(I.cur, x, y, z, I.nx, I.ny, I.nz)) {
+            const double* rho[2] = {rhoA, rhoB};
+            for (int c = 0; c < 2; ++c) {
+                double S[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int i = 1; i < kQ; ++i) {
+                    const int zn = psi_plane(z + ez(i), I.nz, I.wall_z);
+                    const int64_t nb = node_of(wrap(x + ex(i), I.nx), wrap(y + ey(i), I.ny), zn, I.nx, I.ny);
+                    const double r = rho[1 - c][nb];
+                    const double p = I.psi_exp ? 1.0 - exp(-r) : r;
+                    S[0] += wgt(i) * p * ex(i);
+                    S[1] += wgt(i) * p * ey(i);
+                    S[2] += wgt(i) * p * ez(i);
+                }
+                const double r = rho[c][k];
+                const double pc = I.psi_exp ? 1.0 - exp(-r) : r;
+                for (int dd = 0; dd < 3; ++dd) num[dd] += 0.5 * (-pc * I.g * S[dd]);
+            }
+        }
+        const double rt = rhoA[k] + rhoB[k];
+        for (int dd = 0; dd < 3; ++dd) U[(int64_t)dd * I.n + k] = num[dd] / rt;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 diagnostics: one block per z-plane writes plane partials, then one
+// block sums them in a fixed order (deterministic).
+// Partial layout per plane: massA, massB, px, py, pz, phi, flux, nonfinite,
+// nonpositive.
+// ---------------------------------------------------------------------------
+
+constexpr int kDiagVals = 9;
+
+template <typename A>
+__device__ __forceinline__ void block_sum_n(A* vals, int nv, A* lds)
+{
+    // lds: [nv][NT/64]
+    const int t = threadIdx.x, nw = blockDim.x >> 6;
+    for (int q = 0; q < nv; ++q) {
+        A v = block_sum_wave(vals[q]);
+        if ((t & 63) == 0) lds[q * nw + (t >> 6)] = v;
+    }
+    __syncthreads();
+    if (t < nv) {
+        A s = 0;
+        for (int w = 0; w < nw; ++w) s += lds[t * nw + w];
+        lds[t * nw] = s;
+    }
+    __syncthreads();
+    for (int q = 0; q < nv; ++q) vals[q] = lds[q * nw];
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag_planes(Inst I, const T* __restrict__ src, double* __restrict__ part)
+{
+    using A = typename Arith<T>::A;
+    __shared__ double lds[kDiagVals * 4];
+    const T* s = src + I.base;
+    const int z = blockIdx.x;
+    const int area = I.nx * I.ny;
+    double acc[kDiagVals] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = threadIdx.x; k < area; k += blockDim.x) {
+        const int x = k % I.nx, y = k / I.nx;
+        NodeVals<T, A> v;
+        pull_node<T, A>(s, I, x, y, z, v);
+        node_density<T, A>(I, v);
+        if (in_sink(I.reset, x, y, z, I.nx, I.ny, I.nz)) acc[6] += sink_reset<T, A>(I, v);
+        const double ra = (double)v.rho[0], rb = (double)v.rho[1];
+        acc[0] += ra;
+        acc[1] += rb;
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                const double fi = (double)v.f[c][i];
+                acc[2] += fi * ex(i);
+                acc[3] += fi * ey(i);
+                acc[4] += fi * ez(i);
+            }
+        double phi = (ra - rb - I.phi_out) / (I.phi_in - I.phi_out);
+        phi = phi < 0.0 ? 0.0 : (phi > 1.0 ? 1.0 : phi);
+        acc[5] += phi;
+        if (!isfinite(ra) || !isfinite(rb)) acc[7] += 1.0;
+        if (ra <= 0.0 || rb <= 0.0) acc[8] += 1.0;
+    }
+    block_sum_n<double>(acc, kDiagVals, lds);
+    if (threadIdx.x < kDiagVals) part[(int64_t)z * kDiagVals + threadIdx.x] = acc[threadIdx.x];
+}
+
+// out: [0] massA [1] massB [2..4] momentum [5] phi sum [6] pending flux
+//      [7] nonfinite [8] nonpositive [9] booked E [10] z_interface
+template <int NT>
+__global__ __launch_bounds__(NT) void k_diag_final(Inst I, const double* __restrict__ part,
+                                                   const double* __restrict__ eacc, const double* __restrict__ ebase,
+                                                   int inst, double* __restrict__ out)
+{
+    __shared__ double lds[(kDiagVals + 1) * (NT / 64)];
+    double acc[kDiagVals + 1];
+    for (int q = 0; q <= kDiagVals; ++q) acc[q] = 0.0;
+    for (int z = threadIdx.x; z < I.nz; z += NT)
+        for (int q = 0; q < kDiagVals; ++q) acc[q] += part[(int64_t)z * kDiagVals + q];
+    for (int k = I.item_begin + threadIdx.x; k < I.item_end; k += NT) acc[kDiagVals] += eacc[k];
+    block_sum_n<double>(acc, kDiagVals + 1, lds);
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < kDiagVals; ++q) out[q] = acc[q];
+        out[9] = acc[kDiagVals] + ebase[inst];
+        double zi = __builtin_nan("");
+        const double area = (double)I.nx * I.ny;
+        for (int z = 0; z + 1 < I.nz; ++z) {
+            const double a = (part[(int64_t)z * kDiagVals] - part[(int64_t)z * kDiagVals + 1]) / area;
+            const double b = (part[(int64_t)(z + 1) * kDiagVals] - part[(int64_t)(z + 1) * kDiagVals + 1]) / area;
+            if ((a > 0.0 && b <= 0.0) || (a < 0.0 && b >= 0.0)) {
+                zi = z + a / (a - b);
+                break;
+            }
+        }
+        out[10] = zi;
+    }
+}
+
+// Folds the per-item evaporation accumulators of each instance into its base
+// value (used before the work-item list changes), then clears them.
+__global__ void k_fold_eacc(const Inst* __restrict__ insts, int n_inst, double* __restrict__ eacc,
+                            double* __restrict__ ebase)
+{
+    const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+    if (inst >= n_inst) return;
+    const Inst I = insts[inst];
+    double s = 0.0;
+    for (int k = I.item_begin; k < I.item_end; ++k) {
+        s += eacc[k];
+        eacc[k] = 0.0;
+    }
+    ebase[inst] += s;
+}
+
+__global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+
+}  // namespace lbsc

@@ -1,0 +1,117 @@
+// D3Q19 lattice constants and index geometry shared by the kernels and the
+// host runtime of the Shan-Chen evaporation library.
+//
+// Direction order (the paper fixes only the weights, Sec. II A): 0 rest,
+// 1..6 = +x,-x,+y,-y,+z,-z, 7..18 the twelve face diagonals with opposites
+// adjacent. Weights w_0 = 1/3, w_1..6 = 1/18, w_7..18 = 1/36; c_s^2 = 1/3.
+#pragma once
+
+#include <cstdint>
+
+#ifndef LBSC_HD
+#define LBSC_HD __host__ __device__ __forceinline__
+#endif
+
+namespace lbsc {
+
+constexpr int kQ = 19;
+
+// Velocity components packed per direction; kept as constexpr functions so
+// fully unrolled device loops see compile-time constants.
+LBSC_HD constexpr int ex(int i)
+{
+    return (i == 1 || i == 7 || i == 9 || i == 11 || i == 13) ? 1
+         : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14) ? -1 : 0;
+}
+LBSC_HD constexpr int ey(int i)
+{
+    return (i == 3 || i == 7 || i == 10 || i == 15 || i == 17) ? 1
+         : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18) ? -1 : 0;
+}
+LBSC_HD constexpr int ez(int i)
+{
+    return (i == 5 || i == 11 || i == 14 || i == 15 || i == 18) ? 1
+         : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17) ? -1 : 0;
+}
+LBSC_HD constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+LBSC_HD constexpr double wgt(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+// Sink geometry kinds (mirrors the public enum values).
+enum SinkKind : int32_t { kSinkNone = 0, kSinkZmax = 1, kSinkFaces = 2, kSinkSphere = 3 };
+
+struct Sink {
+    int32_t kind;
+    int32_t pad;
+    double rho_h;     // density imposed on component A
+    double r2;        // squared radius of a spherical sink
+    double cx, cy, cz;
+};
+
+LBSC_HD bool in_sink(const Sink& s, int x, int y, int z, int nx, int ny, int nz)
+{
+    switch (s.kind) {
+    case kSinkZmax: return z == nz - 1;
+    case kSinkFaces: return x == 0 || y == 0 || z == 0 || x == nx - 1 || y == ny - 1 || z == nz - 1;
+    case kSinkSphere: {
+        double dx = x - s.cx, dy = y - s.cy, dz = z - s.cz;
+        return dx * dx + dy * dy + dz * dz >= s.r2;
+    }
+    default: return false;
+    }
+}
+
+// Per-instance description, stored in device memory.
+struct Inst {
+    int32_t nx, ny, nz, wall_z;
+    int32_t psi_exp;       // 0: psi = rho, 1: psi = 1 - exp(-rho)
+    int32_t count_reset;   // 0: the next pull-time reset is not booked into E
+    int64_t n;             // nodes
+    int64_t pstride;       // elements between consecutive (c, i) planes
+    int64_t base;          // element offset of this instance in the arena
+    double tau[2];
+    double g;
+    double shift[2];       // rho0^c of shifted storage (0 for plain FP64)
+    double phi_in, phi_out;
+    Sink reset;            // sink that formed the stored state (applied on pull)
+    Sink cur;              // current sink (its nodes skip collision)
+    int32_t item_begin, item_end;   // this instance's work items
+};
+
+// One block's work: an xy tile [x0, x0+tw) x [y0, y0+th) marched over z in
+// [z0, z0+nzc).
+struct Item {
+    int32_t inst;
+    int16_t x0, y0;
+    int16_t tw, th;
+    int16_t z0, nzc;
+};
+
+LBSC_HD int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// Plane index providing psi for a z outside [0, nz): periodic wrap, or the
+// mirror psi(-1) := psi(0), psi(nz) := psi(nz-1) at a wall on the z seam.
+LBSC_HD int psi_plane(int z, int nz, int wall_z)
+{
+    if (z >= 0 && z < nz) return z;
+    if (wall_z) return z < 0 ? 0 : nz - 1;
+    return wrap(z, nz);
+}
+
+// Pull source of population i at node (x, y, z): returns the node the value
+// comes from and whether it is the reflected population opp(i) of the node
+// itself (bounce-back across a wall on the z seam).
+struct PullSrc {
+    int x, y, z;
+    bool reflected;
+};
+
+LBSC_HD PullSrc pull_src(int i, int x, int y, int z, int nx, int ny, int nz, int wall_z)
+{
+    int zs = z - ez(i);
+    if (wall_z && (zs < 0 || zs >= nz)) return PullSrc{x, y, z, true};
+    return PullSrc{wrap(x - ex(i), nx), wrap(y - ey(i), ny), wrap(zs, nz), false};
+}
+
+LBSC_HD int64_t node_of(int x, int y, int z, int nx, int ny) { return ((int64_t)z * ny + y) * nx + x; }
+
+}  // namespace lbsc

@@ -1,0 +1,863 @@
+// Host runtime of the lbsc C ABI (see include/lbsc.h): validation, scratch
+// layout, work-item schedules, launches, HIP graphs, the tile tuner and
+// checkpoints. Device work is in kernels.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbsc.h"
+#include "kernels.h"
+
+using lbsc::Inst;
+using lbsc::Item;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr uint64_t kMagic = 0x4C4253432D434B31ull;  // "LBSC-CK1"
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t elem_size(int prec) { return prec == LBSC_FP64 ? 8 : (prec == LBSC_FP32S ? 4 : 2); }
+
+struct CkptHeader {
+    uint64_t magic;
+    int32_t n_inst, precision;
+    int64_t step;
+    int64_t pop_bytes;
+    int32_t cur, pad;
+};
+
+}  // namespace
+
+struct lbsc_ctx {
+    int n_inst = 0;
+    int precision = 0;
+    size_t elem = 0;
+    std::vector<lbsc_params> params;
+    std::vector<Inst> inst;       // host copy of the device table
+    std::vector<Item> items;
+    lbsc_tiles tiles{0, 0, 0, 0};
+    int nt = 256;
+    size_t pop_elems = 0;         // elements per population buffer
+    size_t max_items = 0;
+    int max_nz = 0;
+    // scratch layout (byte offsets)
+    size_t off_inst = 0, off_items = 0, off_eacc = 0, off_ebase = 0, off_part = 0, off_out = 0, scratch_bytes = 0;
+    // bound buffers
+    void* pop[2] = {nullptr, nullptr};
+    char* scratch = nullptr;
+    bool bound = false;
+    int cur = 0;                  // buffer holding the stored populations
+    int64_t step = 0;
+    hipStream_t stream = nullptr;
+    // graphs
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int graph_steps = 0;
+    std::string err;
+
+    Inst* d_inst() { return reinterpret_cast<Inst*>(scratch + off_inst); }
+    Item* d_items() { return reinterpret_cast<Item*>(scratch + off_items); }
+    double* d_eacc() { return reinterpret_cast<double*>(scratch + off_eacc); }
+    double* d_ebase() { return reinterpret_cast<double*>(scratch + off_ebase); }
+    double* d_part() { return reinterpret_cast<double*>(scratch + off_part); }
+    double* d_out() { return reinterpret_cast<double*>(scratch + off_out); }
+};
+
+namespace {
+
+lbsc_status fail(lbsc_ctx* c, lbsc_status s, const char* fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+#define HIPCHK(ctx, call)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) return fail((ctx), LBSC_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+lbsc::Sink make_sink(int kind, double rho_h, double radius, const double* center)
+{
+    lbsc::Sink s{};
+    s.kind = kind;
+    s.rho_h = rho_h;
+    s.r2 = radius * radius;
+    s.cx = center[0];
+    s.cy = center[1];
+    s.cz = center[2];
+    return s;
+}
+
+bool same_sink(const lbsc::Sink& a, const lbsc::Sink& b)
+{
+    return a.kind == b.kind && a.rho_h == b.rho_h && a.r2 == b.r2 && a.cx == b.cx && a.cy == b.cy && a.cz == b.cz;
+}
+
+lbsc_status validate(const lbsc_params& p, int k, std::string& why)
+{
+    char buf[256];
+    auto bad = [&](const char* m) {
+        snprintf(buf, sizeof buf, "instance %d: %s", k, m);
+        why = buf;
+        return LBSC_E_ARG;
+    };
+    if (p.nx < 1 || p.ny < 1 || p.nz < 1 || p.nx > 4096 || p.ny > 4096 || p.nz > 4096) return bad("size out of 1..4096");
+    if ((int64_t)p.nx * p.ny * p.nz >= (int64_t(1) << 31)) return bad("nx*ny*nz must be < 2^31");
+    if (!(p.tau[0] > 0.5) || !(p.tau[1] > 0.5)) return bad("tau must be > 0.5");
+    if (!std::isfinite(p.g)) return bad("g not finite");
+    if (p.psi != LBSC_PSI_RHO && p.psi != LBSC_PSI_EXP) return bad("unknown psi");
+    if (p.precision < LBSC_FP64 || p.precision > LBSC_FP16S) return bad("unknown precision");
+    if (p.sink < LBSC_SINK_NONE || p.sink > LBSC_SINK_SPHERE) return bad("unknown sink kind");
+    if (!std::isfinite(p.rho_h) || !std::isfinite(p.sink_radius)) return bad("sink parameters not finite");
+    if (p.phi_delta[0] == p.phi_delta[1]) return bad("phi_delta[0] must differ from phi_delta[1]");
+    if (!std::isfinite(p.shift[0]) || !std::isfinite(p.shift[1])) return bad("shift not finite");
+    return LBSC_OK;
+}
+
+// Work items of one instance for the schedule in `t` (see lbsc_tiles).
+void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int64_t total_nodes, std::vector<Item>& out)
+{
+    int tw = t.tw > 0 ? t.tw : (I.nx <= 128 ? I.nx : 64);
+    tw = std::min({tw, I.nx, 128, nt});
+    int th = t.th > 0 ? t.th : std::max(1, nt / tw);
+    th = std::min({th, I.ny, 128, std::max(1, nt / tw)});
+    const int mx = (I.nx + tw - 1) / tw, my = (I.ny + th - 1) / th;
+    const int cols = mx * my;
+    int nzc = t.nzc;
+    if (nzc <= 0) {
+        // About 2048 blocks for the whole context, at least 4 planes per chunk.
+        double want = 2048.0 * (double)I.n / (double)total_nodes / cols;
+        int chunks = std::max(1, (int)std::ceil(want));
+        chunks = std::min(chunks, std::max(1, I.nz / 4));
+        nzc = (I.nz + chunks - 1) / chunks;
+    }
+    nzc = std::min(nzc, I.nz);
+    for (int z0 = 0; z0 < I.nz; z0 += nzc)
+        for (int by = 0; by < my; ++by)
+            for (int bx = 0; bx < mx; ++bx) {
+                Item it{};
+                it.inst = inst;
+                it.x0 = (int16_t)(bx * tw);
+                it.y0 = (int16_t)(by * th);
+                it.tw = (int16_t)std::min(tw, I.nx - bx * tw);
+                it.th = (int16_t)std::min(th, I.ny - by * th);
+                it.z0 = (int16_t)z0;
+                it.nzc = (int16_t)std::min(nzc, I.nz - z0);
+                out.push_back(it);
+            }
+}
+
+lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& items, std::vector<Inst>& inst, int& nt)
+{
+    nt = t.nt > 0 ? t.nt : 256;
+    if (nt != 256 && nt != 512) return fail(c, LBSC_E_ARG, "tiles.nt must be 256 or 512");
+    if (t.tw > 128 || t.th > 128) return fail(c, LBSC_E_ARG, "tiles.tw and tiles.th must be <= 128");
+    int64_t total = 0;
+    for (auto& I : inst) total += I.n;
+    items.clear();
+    for (int k = 0; k < (int)inst.size(); ++k) {
+        inst[k].item_begin = (int32_t)items.size();
+        instance_items(inst[k], k, t, nt, total, items);
+        inst[k].item_end = (int32_t)items.size();
+    }
+    if (items.size() > c->max_items)
+        return fail(c, LBSC_E_ARG, "schedule needs %zu work items, more than the %zu reserved", items.size(),
+                    c->max_items);
+    constexpr int kFoot256 = lbsc::Foot<256>::kMax, kFoot512 = lbsc::Foot<512>::kMax;
+    for (auto& it : items) {
+        if (it.tw * it.th > nt || it.tw > 128 || it.th > 128 ||
+            (it.tw + 2) * (it.th + 2) > (nt == 256 ? kFoot256 : kFoot512))
+            return fail(c, LBSC_E_ARG, "internal: tile %dx%d does not fit %d threads", it.tw, it.th, nt);
+        const Inst& I = inst[it.inst];
+        if (it.x0 < 0 || it.y0 < 0 || it.z0 < 0 || it.x0 + it.tw > I.nx || it.y0 + it.th > I.ny ||
+            it.z0 + it.nzc > I.nz || it.tw < 1 || it.th < 1 || it.nzc < 1)
+            return fail(c, LBSC_E_ARG, "internal: tile outside its lattice");
+    }
+    return LBSC_OK;
+}
+
+lbsc_status upload_table(lbsc_ctx* c)
+{
+    HIPCHK(c, hipMemcpyAsync(c->d_inst(), c->inst.data(), c->inst.size() * sizeof(Inst), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBSC_OK;
+}
+
+lbsc_status upload_items(lbsc_ctx* c)
+{
+    HIPCHK(c, hipMemcpyAsync(c->d_items(), c->items.data(), c->items.size() * sizeof(Item), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBSC_OK;
+}
+
+void drop_graphs(lbsc_ctx* c)
+{
+    for (auto& g : c->gexec)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+int fill_grid(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 65536); }
+
+template <typename T, int NT>
+hipError_t launch_step_t(lbsc_ctx* c, hipStream_t s, int src)
+{
+    const int n = (int)c->items.size();
+    const int grid = ((n + 7) / 8) * 8;
+    hipLaunchKernelGGL((lbsc::k_step<T, NT>), dim3(grid), dim3(NT), 0, s, c->d_inst(), c->d_items(), n,
+                       (const T*)c->pop[src], (T*)c->pop[src ^ 1], c->d_eacc());
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step_p(lbsc_ctx* c, hipStream_t s, int src)
+{
+    return c->nt == 512 ? launch_step_t<T, 512>(c, s, src) : launch_step_t<T, 256>(c, s, src);
+}
+
+hipError_t launch_step(lbsc_ctx* c, hipStream_t s, int src)
+{
+    switch (c->precision) {
+    case LBSC_FP64: return launch_step_p<double>(c, s, src);
+    case LBSC_FP32S: return launch_step_p<float>(c, s, src);
+    default: return launch_step_p<_Float16>(c, s, src);
+    }
+}
+
+bool steady(const lbsc_ctx* c)
+{
+    for (auto& I : c->inst)
+        if (!I.count_reset || !same_sink(I.reset, I.cur)) return false;
+    return true;
+}
+
+lbsc_status check_bound(lbsc_ctx* c)
+{
+    if (!c) return LBSC_E_ARG;
+    if (!c->bound) return fail(c, LBSC_E_STATE, "context has no bound buffers (call lbsc_bind)");
+    return LBSC_OK;
+}
+
+lbsc_status check_inst(lbsc_ctx* c, int inst)
+{
+    lbsc_status s = check_bound(c);
+    if (s) return s;
+    if (inst < 0 || inst >= c->n_inst) return fail(c, LBSC_E_ARG, "instance %d out of range", inst);
+    return LBSC_OK;
+}
+
+template <typename F>
+hipError_t by_precision(int prec, F&& f)
+{
+    switch (prec) {
+    case LBSC_FP64: return f(double{});
+    case LBSC_FP32S: return f(float{});
+    default: return f(_Float16{});
+    }
+}
+
+lbsc_status fold_eacc(lbsc_ctx* c)
+{
+    hipLaunchKernelGGL(lbsc::k_fold_eacc, dim3((c->n_inst + 63) / 64), dim3(64), 0, c->stream, c->d_inst(),
+                       c->n_inst, c->d_eacc(), c->d_ebase());
+    HIPCHK(c, hipGetLastError());
+    return LBSC_OK;
+}
+
+lbsc_status apply_schedule(lbsc_ctx* c, const lbsc_tiles& t)
+{
+    std::vector<Item> items;
+    std::vector<Inst> inst = c->inst;
+    int nt = 256;
+    lbsc_status s = build_items(c, t, items, inst, nt);
+    if (s) return s;
+    if (c->bound) {
+        s = fold_eacc(c);  // accumulators belong to the old item list
+        if (s) return s;
+    }
+    c->items.swap(items);
+    c->inst.swap(inst);
+    c->nt = nt;
+    c->tiles = t;
+    drop_graphs(c);
+    if (c->bound) {
+        if ((s = upload_items(c))) return s;
+        if ((s = upload_table(c))) return s;
+    }
+    return LBSC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbsc_status_string(lbsc_status s)
+{
+    switch (s) {
+    case LBSC_OK: return "ok";
+    case LBSC_E_ARG: return "invalid argument";
+    case LBSC_E_STATE: return "invalid state";
+    case LBSC_E_HIP: return "HIP runtime error";
+    case LBSC_E_NONFINITE: return "non-finite density";
+    case LBSC_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char* lbsc_last_error(const lbsc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+const char* lbsc_version(void) { return "lbsc 0.1 gfx950"; }
+
+lbsc_status lbsc_create(int32_t n_inst, const lbsc_params* params, lbsc_ctx** out)
+{
+    if (!out || !params || n_inst < 1 || n_inst > 65536) return LBSC_E_ARG;
+    *out = nullptr;
+    for (int k = 0; k < n_inst; ++k) {
+        std::string why;
+        if (validate(params[k], k, why)) return LBSC_E_ARG;
+        if (params[k].precision != params[0].precision) return LBSC_E_ARG;
+    }
+    lbsc_ctx* c = new lbsc_ctx();
+    c->n_inst = n_inst;
+    c->precision = params[0].precision;
+    c->elem = elem_size(c->precision);
+    c->params.assign(params, params + n_inst);
+    size_t off = 0;
+    int64_t total_nodes = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        const lbsc_params& p = params[k];
+        Inst I{};
+        I.nx = p.nx; I.ny = p.ny; I.nz = p.nz; I.wall_z = p.wall_z ? 1 : 0;
+        I.psi_exp = p.psi == LBSC_PSI_EXP;
+        I.count_reset = 0;
+        I.n = (int64_t)p.nx * p.ny * p.nz;
+        I.pstride = (int64_t)align_up((size_t)I.n, 256);
+        I.base = (int64_t)off;
+        off += (size_t)(2 * lbsc::kQ) * (size_t)I.pstride;
+        I.tau[0] = p.tau[0]; I.tau[1] = p.tau[1];
+        I.g = p.g;
+        I.shift[0] = c->precision == LBSC_FP64 ? 0.0 : p.shift[0];
+        I.shift[1] = c->precision == LBSC_FP64 ? 0.0 : p.shift[1];
+        I.phi_in = p.phi_delta[0]; I.phi_out = p.phi_delta[1];
+        I.reset = make_sink(p.sink, p.rho_h, p.sink_radius, p.center);
+        I.cur = I.reset;
+        c->inst.push_back(I);
+        total_nodes += I.n;
+        c->max_nz = std::max(c->max_nz, p.nz);
+    }
+    c->pop_elems = off;
+    // Bound on work items: any schedule with tiles of >= 16 nodes per plane.
+    c->max_items = std::max<size_t>(65536, (size_t)(total_nodes / 16) + 64 * (size_t)n_inst);
+    size_t o = 0;
+    c->off_inst = o; o = align_up(o + n_inst * sizeof(Inst), kAlign);
+    c->off_items = o; o = align_up(o + c->max_items * sizeof(Item), kAlign);
+    c->off_eacc = o; o = align_up(o + c->max_items * sizeof(double), kAlign);
+    c->off_ebase = o; o = align_up(o + n_inst * sizeof(double), kAlign);
+    c->off_part = o; o = align_up(o + (size_t)c->max_nz * lbsc::kDiagVals * sizeof(double), kAlign);
+    c->off_out = o; o = align_up(o + 64 * sizeof(double), kAlign);
+    c->scratch_bytes = o;
+    lbsc_tiles t{0, 0, 0, 0};
+    if (apply_schedule(c, t)) {
+        delete c;
+        return LBSC_E_ARG;
+    }
+    *out = c;
+    return LBSC_OK;
+}
+
+lbsc_status lbsc_destroy(lbsc_ctx* ctx)
+{
+    if (!ctx) return LBSC_E_ARG;
+    drop_graphs(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    delete ctx;
+    return LBSC_OK;
+}
+
+lbsc_status lbsc_required_bytes(const lbsc_ctx* ctx, size_t* pop_bytes, size_t* scratch_bytes)
+{
+    if (!ctx || !pop_bytes || !scratch_bytes) return LBSC_E_ARG;
+    *pop_bytes = ctx->pop_elems * ctx->elem;
+    *scratch_bytes = ctx->scratch_bytes;
+    return LBSC_OK;
+}
+
+lbsc_status lbsc_set_stream(lbsc_ctx* ctx, void* hip_stream)
+{
+    if (!ctx) return LBSC_E_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return LBSC_OK;
+}
+
+lbsc_status lbsc_bind(lbsc_ctx* c, void* pop0, void* pop1, void* scratch)
+{
+    if (!c) return LBSC_E_ARG;
+    if (!pop0 || !pop1 || !scratch || pop0 == pop1)
+        return fail(c, LBSC_E_ARG, "bind: need two distinct population buffers and a scratch buffer");
+    if (((uintptr_t)pop0 | (uintptr_t)pop1 | (uintptr_t)scratch) % kAlign)
+        return fail(c, LBSC_E_ARG, "bind: buffers must be %zu-byte aligned", kAlign);
+    c->pop[0] = pop0;
+    c->pop[1] = pop1;
+    c->scratch = (char*)scratch;
+    c->bound = true;
+    c->cur = 0;
+    drop_graphs(c);
+    const int64_t nacc = (int64_t)(c->max_items + c->n_inst);
+    hipLaunchKernelGGL(lbsc::k_fill_f64, dim3(fill_grid(c->max_items)), dim3(256), 0, c->stream, c->d_eacc(),
+                       (int64_t)c->max_items, 0.0);
+    HIPCHK(c, hipGetLastError());
+    hipLaunchKernelGGL(lbsc::k_fill_f64, dim3(1), dim3(256), 0, c->stream, c->d_ebase(), (int64_t)c->n_inst, 0.0);
+    HIPCHK(c, hipGetLastError());
+    (void)nacc;
+    lbsc_status s = upload_items(c);
+    if (s) return s;
+    return upload_table(c);
+}
+
+static lbsc_status begin_init(lbsc_ctx* c, int inst)
+{
+    lbsc_status s = check_inst(c, inst);
+    if (s) return s;
+    // Clear this instance's evaporation accumulators.
+    Inst& I = c->inst[inst];
+    const int nit = I.item_end - I.item_begin;
+    if (nit > 0) {
+        hipLaunchKernelGGL(lbsc::k_fill_f64, dim3(fill_grid(nit)), dim3(256), 0, c->stream, c->d_eacc() + I.item_begin,
+                           (int64_t)nit, 0.0);
+        HIPCHK(c, hipGetLastError());
+    }
+    hipLaunchKernelGGL(lbsc::k_fill_f64, dim3(1), dim3(64), 0, c->stream, c->d_ebase() + inst, (int64_t)1, 0.0);
+    HIPCHK(c, hipGetLastError());
+    I.count_reset = 0;
+    I.reset = I.cur;
+    c->step = 0;
+    return LBSC_OK;
+}
+
+lbsc_status lbsc_init_from_density(lbsc_ctx* c, int32_t inst, const double* rhoA, const double* rhoB)
+{
+    lbsc_status s = begin_init(c, inst);
+    if (s) return s;
+    if (!rhoA || !rhoB) return fail(c, LBSC_E_ARG, "init: null density pointer");
+    const Inst I = c->inst[inst];
+    HIPCHK(c, by_precision(c->precision, [&](auto tag) {
+               using T = decltype(tag);
+               hipLaunchKernelGGL(lbsc::k_init_density<T>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I, rhoA,
+                                  rhoB, (T*)c->pop[c->cur]);
+               return hipGetLastError();
+           }));
+    return upload_table(c);
+}
+
+lbsc_status lbsc_init_from_populations(lbsc_ctx* c, int32_t inst, const double* f)
+{
+    lbsc_status s = begin_init(c, inst);
+    if (s) return s;
+    if (!f) return fail(c, LBSC_E_ARG, "init: null population pointer");
+    const Inst I = c->inst[inst];
+    HIPCHK(c, by_precision(c->precision, [&](auto tag) {
+               using T = decltype(tag);
+               hipLaunchKernelGGL(lbsc::k_init_pops<T>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I, f,
+                                  (T*)c->pop[c->cur]);
+               return hipGetLastError();
+           }));
+    return upload_table(c);
+}
+
+lbsc_status lbsc_set_sink(lbsc_ctx* c, int32_t inst, int32_t kind, double rho_h, double radius)
+{
+    lbsc_status s = check_inst(c, inst);
+    if (s) return s;
+    if (kind < LBSC_SINK_NONE || kind > LBSC_SINK_SPHERE || !std::isfinite(rho_h) || !std::isfinite(radius))
+        return fail(c, LBSC_E_ARG, "set_sink: bad kind or value");
+    c->params[inst].sink = kind;
+    c->params[inst].rho_h = rho_h;
+    c->params[inst].sink_radius = radius;
+    c->inst[inst].cur = make_sink(kind, rho_h, radius, c->params[inst].center);
+    return upload_table(c);
+}
+
+lbsc_status lbsc_set_graph(lbsc_ctx* c, int32_t steps)
+{
+    if (!c) return LBSC_E_ARG;
+    if (steps != 0 && (steps < 2 || (steps & 1))) return fail(c, LBSC_E_ARG, "graph steps must be 0 or even >= 2");
+    drop_graphs(c);
+    c->graph_steps = steps;
+    return LBSC_OK;
+}
+
+static lbsc_status graph_for(lbsc_ctx* c, int parity, hipGraphExec_t* out)
+{
+    if (!c->gexec[parity]) {
+        if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t le = hipSuccess;
+        for (int k = 0; k < c->graph_steps && le == hipSuccess; ++k) le = launch_step(c, c->cap_stream, parity ^ (k & 1));
+        hipGraph_t g = nullptr;
+        hipError_t ee = hipStreamEndCapture(c->cap_stream, &g);
+        if (le != hipSuccess || ee != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(c, LBSC_E_HIP, "graph capture failed: %s", hipGetErrorString(le != hipSuccess ? le : ee));
+        }
+        hipError_t ie = hipGraphInstantiate(&c->gexec[parity], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) return fail(c, LBSC_E_HIP, "graph instantiate: %s", hipGetErrorString(ie));
+    }
+    *out = c->gexec[parity];
+    return LBSC_OK;
+}
+
+lbsc_status lbsc_step(lbsc_ctx* c, int64_t n)
+{
+    lbsc_status s = check_bound(c);
+    if (s) return s;
+    if (n < 0) return fail(c, LBSC_E_ARG, "negative step count");
+    while (n > 0) {
+        if (!steady(c)) {
+            HIPCHK(c, launch_step(c, c->stream, c->cur));
+            c->cur ^= 1;
+            c->step += 1;
+            n -= 1;
+            for (auto& I : c->inst) {
+                I.count_reset = 1;
+                I.reset = I.cur;
+            }
+            if ((s = upload_table(c))) return s;
+            continue;
+        }
+        if (c->graph_steps > 0 && n >= c->graph_steps) {
+            hipGraphExec_t g;
+            if ((s = graph_for(c, c->cur, &g))) return s;
+            HIPCHK(c, hipGraphLaunch(g, c->stream));
+            c->step += c->graph_steps;
+            n -= c->graph_steps;
+            continue;
+        }
+        HIPCHK(c, launch_step(c, c->stream, c->cur));
+        c->cur ^= 1;
+        c->step += 1;
+        n -= 1;
+    }
+    return LBSC_OK;
+}
+
+lbsc_status lbsc_set_tiles(lbsc_ctx* c, const lbsc_tiles* t)
+{
+    if (!c || !t) return LBSC_E_ARG;
+    return apply_schedule(c, *t);
+}
+
+lbsc_status lbsc_num_items(const lbsc_ctx* c, int32_t* n)
+{
+    if (!c || !n) return LBSC_E_ARG;
+    *n = (int32_t)c->items.size();
+    return LBSC_OK;
+}
+
+lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
+{
+    lbsc_status s = check_bound(c);
+    if (s) return s;
+    if (steps < 2) return fail(c, LBSC_E_ARG, "tune: steps must be >= 2");
+    std::vector<lbsc_tiles> cands;
+    for (int nt : {256, 512})
+        for (int tw : {0, 32, 64, 128})
+            for (int nzc : {0, 8, 16, 32, 64}) cands.push_back(lbsc_tiles{nt, tw, 0, nzc});
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    const lbsc_tiles before = c->tiles;
+    const int graph_before = c->graph_steps;
+    c->graph_steps = 0;
+    float best = 1e30f;
+    lbsc_tiles best_t = before;
+    std::vector<std::string> seen;
+    for (const auto& t : cands) {
+        if (apply_schedule(c, t) != LBSC_OK) continue;
+        // Skip schedules identical to one already timed.
+        std::string key(reinterpret_cast<const char*>(c->items.data()), c->items.size() * sizeof(Item));
+        key += std::to_string(c->nt);
+        if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
+        seen.push_back(key);
+        if ((s = lbsc_step(c, 2))) break;  // warm-up
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        if ((s = lbsc_step(c, steps))) break;
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            best_t = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s) return s;
+    c->graph_steps = graph_before;
+    if ((s = apply_schedule(c, best_t))) return s;
+    if (chosen) {
+        *chosen = best_t;
+        chosen->nt = c->nt;
+    }
+    return LBSC_OK;
+}
+
+lbsc_status lbsc_read_density(lbsc_ctx* c, int32_t inst, int32_t comp, double* out)
+{
+    lbsc_status s = check_inst(c, inst);
+    if (s) return s;
+    if (!out || comp < 0 || comp > 1) return fail(c, LBSC_E_ARG, "read_density: bad component or pointer");
+    const Inst I = c->inst[inst];
+    HIPCHK(c, by_precision(c->precision, [&](auto tag) {
+               using T = decltype(tag);
+               hipLaunchKernelGGL(lbsc::k_read_density<T>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
+                                  (const T*)c->pop[c->cur], comp == 0 ? out : nullptr, comp == 1 ? out : nullptr);
+               return hipGetLastError();
+           }));
+    return LBSC_OK;
+}
+
+lbsc_status lbsc_read_observables(lbsc_ctx* c, int32_t inst, double* ra, double* rb, double* u)
+{
+    lbsc_status s = check_inst(c, inst);
+    if (s) return s;
+    if (u && (!ra || !rb)) return fail(c, LBSC_E_ARG, "read_observables: velocity needs both density arrays");
+    const Inst I = c->inst[inst];
+    HIPCHK(c, by_precision(c->precision, [&](auto tag) {
+               using T = decltype(tag);
+               if (ra || rb)
+                   hipLaunchKernelGGL(lbsc::k_read_density<T>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
+                                      (const T*)c->pop[c->cur], ra, rb);
+               hipError_t e = hipGetLastError();
+               if (e != hipSuccess || !u) return e;
+               hipLaunchKernelGGL(lbsc::k_read_velocity<T>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
+                                  (const T*)c->pop[c->cur], (const double*)ra, (const double*)rb, u);
+               return hipGetLastError();
+           }));
+    return LBSC_OK;
+}
+
+lbsc_status lbsc_read_populations(lbsc_ctx* c, int32_t inst, double* f)
+{
+    lbsc_status s = check_inst(c, inst);
+    if (s) return s;
+    if (!f) return fail(c, LBSC_E_ARG, "read_populations: null pointer");
+    const Inst I = c->inst[inst];
+    HIPCHK(c, by_precision(c->precision, [&](auto tag) {
+               using T = decltype(tag);
+               hipLaunchKernelGGL(lbsc::k_read_pops<T>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
+                                  (const T*)c->pop[c->cur], f);
+               return hipGetLastError();
+           }));
+    return LBSC_OK;
+}
+
+lbsc_status lbsc_diagnostics(lbsc_ctx* c, int32_t inst, lbsc_diag* out)
+{
+    lbsc_status s = check_inst(c, inst);
+    if (s) return s;
+    if (!out) return fail(c, LBSC_E_ARG, "diagnostics: null output");
+    const Inst I = c->inst[inst];
+    HIPCHK(c, by_precision(c->precision, [&](auto tag) {
+               using T = decltype(tag);
+               hipLaunchKernelGGL(lbsc::k_diag_planes<T>, dim3(I.nz), dim3(256), 0, c->stream, I,
+                                  (const T*)c->pop[c->cur], c->d_part());
+               return hipGetLastError();
+           }));
+    hipLaunchKernelGGL(lbsc::k_diag_final<256>, dim3(1), dim3(256), 0, c->stream, I, (const double*)c->d_part(),
+                       (const double*)c->d_eacc(), (const double*)c->d_ebase(), inst, c->d_out());
+    HIPCHK(c, hipGetLastError());
+    double h[16];
+    HIPCHK(c, hipMemcpyAsync(h, c->d_out(), 11 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    out->step = c->step;
+    out->mass[0] = h[0];
+    out->mass[1] = h[1];
+    out->momentum[0] = h[2];
+    out->momentum[1] = h[3];
+    out->momentum[2] = h[4];
+    out->r_droplet = std::cbrt(3.0 * h[5] / (4.0 * M_PI));
+    out->evap_rate = h[6];
+    out->evaporated = h[9] + (I.count_reset ? h[6] : 0.0);
+    out->nonfinite = (int64_t)h[7];
+    out->nonpositive = (int64_t)h[8];
+    out->z_interface = h[10];
+    if (out->nonfinite > 0) return fail(c, LBSC_E_NONFINITE, "instance %d: %lld nodes with non-finite density", inst,
+                                        (long long)out->nonfinite);
+    return LBSC_OK;
+}
+
+lbsc_status lbsc_checkpoint_bytes(const lbsc_ctx* c, size_t* bytes)
+{
+    if (!c || !bytes) return LBSC_E_ARG;
+    *bytes = align_up(sizeof(CkptHeader) + c->inst.size() * sizeof(Inst), kAlign) + c->pop_elems * c->elem +
+             align_up(c->n_inst * sizeof(double), kAlign);
+    return LBSC_OK;
+}
+
+lbsc_status lbsc_save(lbsc_ctx* c, void* blob)
+{
+    lbsc_status s = check_bound(c);
+    if (s) return s;
+    if (!blob || (uintptr_t)blob % kAlign) return fail(c, LBSC_E_ARG, "save: blob must be non-null and aligned");
+    if ((s = fold_eacc(c))) return s;
+    std::vector<char> head(align_up(sizeof(CkptHeader) + c->inst.size() * sizeof(Inst), kAlign), 0);
+    CkptHeader h{kMagic, c->n_inst, c->precision, c->step, (int64_t)(c->pop_elems * c->elem), c->cur, 0};
+    memcpy(head.data(), &h, sizeof h);
+    memcpy(head.data() + sizeof h, c->inst.data(), c->inst.size() * sizeof(Inst));
+    char* b = (char*)blob;
+    HIPCHK(c, hipMemcpyAsync(b, head.data(), head.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(b + head.size(), c->pop[c->cur], c->pop_elems * c->elem, hipMemcpyDeviceToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(b + head.size() + c->pop_elems * c->elem, c->d_ebase(), c->n_inst * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBSC_OK;
+}
+
+lbsc_status lbsc_load(lbsc_ctx* c, const void* blob)
+{
+    lbsc_status s = check_bound(c);
+    if (s) return s;
+    if (!blob || (uintptr_t)blob % kAlign) return fail(c, LBSC_E_ARG, "load: blob must be non-null and aligned");
+    std::vector<char> head(align_up(sizeof(CkptHeader) + c->inst.size() * sizeof(Inst), kAlign), 0);
+    const char* b = (const char*)blob;
+    HIPCHK(c, hipMemcpyAsync(head.data(), b, head.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    CkptHeader h;
+    memcpy(&h, head.data(), sizeof h);
+    if (h.magic != kMagic || h.n_inst != c->n_inst || h.precision != c->precision ||
+        h.pop_bytes != (int64_t)(c->pop_elems * c->elem))
+        return fail(c, LBSC_E_ARG, "load: checkpoint does not match this context");
+    std::vector<Inst> saved(c->inst.size());
+    memcpy(saved.data(), head.data() + sizeof h, saved.size() * sizeof(Inst));
+    for (size_t k = 0; k < saved.size(); ++k) {
+        const Inst &a = saved[k], &b2 = c->inst[k];
+        if (a.nx != b2.nx || a.ny != b2.ny || a.nz != b2.nz || a.base != b2.base || a.pstride != b2.pstride)
+            return fail(c, LBSC_E_ARG, "load: instance %zu geometry differs", k);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->pop[c->cur], b + head.size(), c->pop_elems * c->elem, hipMemcpyDeviceToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_ebase(), b + head.size() + c->pop_elems * c->elem, c->n_inst * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
+    hipLaunchKernelGGL(lbsc::k_fill_f64, dim3(fill_grid(c->max_items)), dim3(256), 0, c->stream, c->d_eacc(),
+                       (int64_t)c->max_items, 0.0);
+    HIPCHK(c, hipGetLastError());
+    for (size_t k = 0; k < saved.size(); ++k) {
+        Inst& I = c->inst[k];
+        I.count_reset = saved[k].count_reset;
+        I.reset = saved[k].reset;
+        I.cur = saved[k].cur;
+        c->params[k].sink = I.cur.kind;
+        c->params[k].rho_h = I.cur.rho_h;
+        c->params[k].sink_radius = std::sqrt(I.cur.r2);
+    }
+    c->step = h.step;
+    return upload_table(c);
+}
+
+int32_t lbsc_selftest(void)
+{
+    using namespace lbsc;
+    int bad = 0;
+    // Lattice: opposites, weights, isotropy up to second order.
+    double sw = 0, s1[3] = {0, 0, 0}, s2[3][3] = {{0}};
+    for (int i = 0; i < kQ; ++i) {
+        if (ex(opp(i)) != -ex(i) || ey(opp(i)) != -ey(i) || ez(opp(i)) != -ez(i)) ++bad;
+        const int e2 = ex(i) * ex(i) + ey(i) * ey(i) + ez(i) * ez(i);
+        if (wgt(i) != (e2 == 0 ? 1.0 / 3.0 : (e2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0))) ++bad;
+        for (int j = 0; j < i; ++j)
+            if (ex(i) == ex(j) && ey(i) == ey(j) && ez(i) == ez(j)) ++bad;
+        const int e[3] = {ex(i), ey(i), ez(i)};
+        sw += wgt(i);
+        for (int a = 0; a < 3; ++a) {
+            s1[a] += wgt(i) * e[a];
+            for (int b = 0; b < 3; ++b) s2[a][b] += wgt(i) * e[a] * e[b];
+        }
+    }
+    if (std::fabs(sw - 1.0) > 1e-15) ++bad;
+    for (int a = 0; a < 3; ++a) {
+        if (std::fabs(s1[a]) > 1e-15) ++bad;
+        for (int b = 0; b < 3; ++b)
+            if (std::fabs(s2[a][b] - (a == b ? 1.0 / 3.0 : 0.0)) > 1e-15) ++bad;
+    }
+    // Pulls form a permutation of the stored slots, with and without a wall,
+    // and the inverse mapping used by the init kernels agrees with it.
+    for (int wall = 0; wall < 2; ++wall) {
+        const int nx = 3, ny = 2, nz = 4;
+        std::vector<int> hits(kQ * nx * ny * nz, 0);
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x)
+                    for (int i = 0; i < kQ; ++i) {
+                        PullSrc s = pull_src(i, x, y, z, nx, ny, nz, wall);
+                        const int q = s.reflected ? opp(i) : i;
+                        if (s.x < 0 || s.x >= nx || s.y < 0 || s.y >= ny || s.z < 0 || s.z >= nz) ++bad;
+                        else hits[q * nx * ny * nz + (int)node_of(s.x, s.y, s.z, nx, ny)] += 1;
+                        // inverse: slot (q, src) -> target node/population
+                        const int zt = s.z + ez(q);
+                        int tx, ty, tz, ti;
+                        if (wall && (zt < 0 || zt >= nz)) { tx = s.x; ty = s.y; tz = s.z; ti = opp(q); }
+                        else { tx = wrap(s.x + ex(q), nx); ty = wrap(s.y + ey(q), ny); tz = wrap(zt, nz); ti = q; }
+                        if (tx != x || ty != y || tz != z || ti != i) ++bad;
+                    }
+        for (int h : hits)
+            if (h != 1) ++bad;
+    }
+    // psi planes stay in range.
+    for (int nz : {1, 2, 5})
+        for (int wall = 0; wall < 2; ++wall)
+            for (int z = -1; z <= nz; ++z) {
+                const int p = psi_plane(z, nz, wall);
+                if (p < 0 || p >= nz) ++bad;
+            }
+    // Work items tile every lattice exactly once.
+    const int dims[][3] = {{4, 4, 128}, {128, 128, 128}, {48, 48, 48}, {156, 156, 156}, {1, 1, 64}, {200, 7, 9}};
+    for (auto& d : dims)
+        for (int nt : {256, 512})
+            for (int tw : {0, 32, 64, 128})
+                for (int nzc : {0, 4, 16}) {
+                    Inst I{};
+                    I.nx = d[0]; I.ny = d[1]; I.nz = d[2];
+                    I.n = (int64_t)d[0] * d[1] * d[2];
+                    std::vector<Item> items;
+                    instance_items(I, 0, lbsc_tiles{nt, tw, 0, nzc}, nt, I.n, items);
+                    std::vector<unsigned char> cover((size_t)I.n, 0);
+                    for (auto& it : items) {
+                        if (it.tw * it.th > nt || it.tw > 128 || it.th > 128) ++bad;
+                        if ((it.tw + 2) * (it.th + 2) > (nt == 256 ? Foot<256>::kMax : Foot<512>::kMax)) ++bad;
+                        for (int z = it.z0; z < it.z0 + it.nzc; ++z)
+                            for (int y = it.y0; y < it.y0 + it.th; ++y)
+                                for (int x = it.x0; x < it.x0 + it.tw; ++x) {
+                                    if (x >= I.nx || y >= I.ny || z >= I.nz) { ++bad; continue; }
+                                    cover[(size_t)node_of(x, y, z, I.nx, I.ny)] += 1;
+                                }
+                    }
+                    for (auto v : cover)
+                        if (v != 1) { ++bad; break; }
+                }
+    return bad;
+}
+
+}  // extern "C"

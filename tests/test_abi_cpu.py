@@ -1,0 +1,83 @@
+"""The C-ABI library loads without a GPU, exports every declared entry point,
+passes its host self-test and validates parameters (no device work)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1701_03637_amd import lbsc
+    return lbsc.load_library()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "lbsc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbsc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_header():
+    from paper_1701_03637_amd import lbsc
+    assert sorted(lbsc.SYMBOLS) == declared_functions()
+
+
+def test_host_selftest(lib):
+    assert lib.lbsc_selftest() == 0
+
+
+def test_create_validates_and_sizes(lib):
+    from paper_1701_03637_amd import lbsc
+    h = ctypes.c_void_p()
+    p = lbsc.make_params(64, 48, 40, precision="fp32s", sink="faces")
+    assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == 0
+    pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.lbsc_required_bytes(h, ctypes.byref(pb), ctypes.byref(sb)) == 0
+    n = 64 * 48 * 40
+    assert pb.value == 38 * ((n + 255) // 256 * 256) * 4
+    nit = ctypes.c_int32()
+    assert lib.lbsc_num_items(h, ctypes.byref(nit)) == 0 and nit.value > 0
+    # calls that need device buffers report an unbound context
+    assert lib.lbsc_step(h, 1) == -2
+    assert b"lbsc_bind" in lib.lbsc_last_error(h)
+    assert lib.lbsc_destroy(h) == 0
+    for bad in (dict(nx=0), dict(tau=(0.5, 1.0)), dict(precision=7), dict(sink=9), dict(phi_delta=(0.1, 0.1))):
+        q = lbsc.make_params(8, 8, 8)
+        for k, v in bad.items():
+            if k == "tau":
+                q.tau[0], q.tau[1] = v
+            elif k == "phi_delta":
+                q.phi_delta[0], q.phi_delta[1] = v
+            else:
+                setattr(q, k, v)
+        assert lib.lbsc_create(1, ctypes.byref(q), ctypes.byref(h)) == -1, bad
+    # mixed precisions in one context are rejected
+    two = (lbsc.Params * 2)(lbsc.make_params(8, 8, 8, precision="fp32s"), lbsc.make_params(8, 8, 8))
+    assert lib.lbsc_create(2, two, ctypes.byref(h)) == -1
+    assert lib.lbsc_status_string(-4) == b"non-finite density"
+
+
+def test_tile_schedule_errors(lib):
+    from paper_1701_03637_amd import lbsc
+    h = ctypes.c_void_p()
+    p = lbsc.make_params(32, 32, 32)
+    assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == 0
+    for t in (lbsc.Tiles(128, 0, 0, 0), lbsc.Tiles(256, 200, 0, 0)):
+        assert lib.lbsc_set_tiles(h, ctypes.byref(t)) == -1
+    assert lib.lbsc_set_tiles(h, ctypes.byref(lbsc.Tiles(512, 32, 16, 4))) == 0
+    nit = ctypes.c_int32()
+    lib.lbsc_num_items(h, ctypes.byref(nit))
+    assert nit.value == 1 * 2 * 8
+    assert lib.lbsc_set_graph(h, 3) == -1 and lib.lbsc_set_graph(h, 4) == 0
+    lib.lbsc_destroy(h)

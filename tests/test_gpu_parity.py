@@ -1,0 +1,230 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances:
+  FP64  - populations within 1e-12 of max|f| (rounding order only);
+  FP32S - densities within 1e-5, populations within 2e-6 of max|f|;
+  FP16S - densities within 1e-3.
+They are derived from the storage unit roundoff (2^-24, 2^-11 of the stored
+deviation) accumulated over the steps of each case; see the design notes.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import lbinputs as li
+from oracle.oracle import (PSI_EXP, PSI_RHO, SINK_FACES, SINK_NONE, SINK_SPHERE, SINK_ZMAX, Oracle,
+                           OracleParams)
+
+pytestmark = pytest.mark.gpu
+
+SINK_CODE = {"none": SINK_NONE, "zmax": SINK_ZMAX, "faces": SINK_FACES, "sphere": SINK_SPHERE}
+
+
+@pytest.fixture(scope="module")
+def lb():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_1701_03637_amd as lb
+    lb.load_library()
+    return lb
+
+
+def _pair(lb, nx, ny, nz, *, precision="fp64", psi="rho", g=0.9, tau=(1.0, 1.0), wall_z=False, sink="none",
+          rho_h=0.04, sink_radius=0.0, shift=(0.04, 0.70), phi_delta=(0.66, -0.66)):
+    p = lb.make_params(nx, ny, nz, wall_z=wall_z, tau=tau, g=g, psi=psi, precision=precision, shift=shift,
+                       sink=sink, rho_h=rho_h, sink_radius=sink_radius, phi_delta=phi_delta)
+    sim = lb.Sim(p)
+    orc = Oracle(OracleParams(nx, ny, nz, wall_z=wall_z, tau=tau, g=g, psi=PSI_EXP if psi == "exp" else PSI_RHO,
+                              sink=SINK_CODE[sink], rho_h=rho_h, sink_radius=sink_radius, phi_delta=phi_delta))
+    return sim, orc
+
+
+def _cmp_pops(sim, orc, tol_rel):
+    got = sim.populations().cpu().numpy()
+    ref = orc.populations()
+    err = np.max(np.abs(got - ref))
+    scale = np.max(np.abs(ref))
+    assert err <= tol_rel * scale, f"max |df| = {err:.3e} (scale {scale:.3e})"
+    return err
+
+
+@pytest.mark.parametrize("case", [
+    dict(dims=(13, 7, 9), psi="exp", g=2.2, sink="none", wall_z=False, steps=6),
+    dict(dims=(13, 7, 9), psi="rho", g=0.9, sink="zmax", wall_z=True, steps=6),
+    dict(dims=(9, 10, 11), psi="exp", g=1.5, sink="faces", wall_z=False, steps=5),
+    dict(dims=(11, 11, 11), psi="rho", g=0.9, sink="sphere", wall_z=False, steps=5, sink_radius=4.2,
+         tau=(0.8, 1.3)),
+    dict(dims=(1, 1, 16), psi="exp", g=3.6, sink="zmax", wall_z=True, steps=8),
+    dict(dims=(70, 3, 5), psi="rho", g=1.1, sink="faces", wall_z=False, steps=4),
+])
+def test_fp64_random_populations_match_oracle(lb, case):
+    nx, ny, nz = case["dims"]
+    sim, orc = _pair(lb, nx, ny, nz, psi=case["psi"], g=case["g"], sink=case["sink"], wall_z=case["wall_z"],
+                     rho_h=0.03, sink_radius=case.get("sink_radius", 0.0), tau=case.get("tau", (1.0, 1.0)))
+    f0 = li.random_populations(nx, ny, nz, seed=7, base_a=0.3, base_b=0.4, amp=0.05)
+    sim.init_from_populations(f0)
+    orc.init_from_populations(f0)
+    _cmp_pops(sim, orc, 1e-14)   # initial sink reset
+    for _ in range(case["steps"]):
+        sim.step(1)
+        orc.step(1)
+    _cmp_pops(sim, orc, 1e-12)
+    dg, do = sim.diagnostics(), orc.diagnostics()
+    tot = do["mass"][0] + do["mass"][1]
+    for c in range(2):
+        assert abs(dg["mass"][c] - do["mass"][c]) <= 1e-13 * tot
+    assert abs(dg["evaporated"] - do["evaporated"]) <= 1e-13 * tot
+    assert abs(dg["evap_rate"] - do["evap_rate"]) <= 1e-13 * tot
+    assert np.allclose(dg["momentum"], do["momentum"], atol=1e-12 * tot, rtol=0)
+
+
+def test_fp64_film_config_full_run(lb):
+    """4x4x128 film, psi = rho, g = 0.9, sink on z = 127, wall, 1000 steps."""
+    w = li.film_small()
+    sim, orc = _pair(lb, w.nx, w.ny, w.nz, psi=w.psi, g=w.g, sink=w.sink, wall_z=w.wall_z, rho_h=w.rho_h)
+    a, b = w.densities()
+    sim.init_from_density(a, b)
+    orc.init_from_density(a, b)
+    for chunk in (1, 99, 400, 500):
+        sim.step(chunk)
+        orc.step(chunk)
+        _cmp_pops(sim, orc, 1e-12)
+    dg, do = sim.diagnostics(), orc.diagnostics()
+    assert dg["step"] == do["step"] == 1000
+    tot = do["mass"][0] + do["mass"][1]
+    assert abs(dg["mass"][0] - do["mass"][0]) <= 1e-13 * tot
+    assert abs(dg["evaporated"] - do["evaporated"]) <= 1e-13 * tot
+    assert abs(dg["z_interface"] - do["z_interface"]) <= 1e-9
+    ra, rb, u = sim.observables()
+    ora, orb = orc.density()
+    ou = orc.velocity()
+    assert np.max(np.abs(ra.cpu().numpy() - ora)) < 1e-13
+    assert np.max(np.abs(u.cpu().numpy() - ou)) < 1e-13
+
+
+def test_fp64_droplet_ragged_tiles_and_sink_switch(lb):
+    """Droplet in 37x29x33 (ragged tiles), equilibrated without sink, then the
+    sink is switched on mid-run (Sec. III C workflow)."""
+    nx, ny, nz = 37, 29, 33
+    sim, orc = _pair(lb, nx, ny, nz, psi="exp", g=3.6, sink="none", rho_h=0.02, phi_delta=(0.675, -0.675))
+    a, b = li.droplet(nx, ny, nz, 8.0)
+    sim.init_from_density(a, b)
+    orc.init_from_density(a, b)
+    sim.step(30)
+    orc.step(30)
+    _cmp_pops(sim, orc, 1e-12)
+    sim.set_sink("sphere", 0.02, 13.5)
+    orc.set_sink(SINK_SPHERE, 0.02, 13.5)
+    d_s, d_o = sim.diagnostics(), orc.diagnostics()
+    assert abs(d_s["evaporated"] - d_o["evaporated"]) < 1e-12
+    sim.step(40)
+    orc.step(40)
+    _cmp_pops(sim, orc, 1e-12)
+    d_s, d_o = sim.diagnostics(), orc.diagnostics()
+    assert abs(d_s["evaporated"] - d_o["evaporated"]) <= 1e-12 * d_o["mass"][0]
+    assert abs(d_s["r_droplet"] - d_o["r_droplet"]) <= 1e-10
+    sim.set_sink("none", 0.02, 0.0)
+    orc.set_sink(SINK_NONE, 0.02, 0.0)
+    sim.step(5)
+    orc.step(5)
+    _cmp_pops(sim, orc, 1e-12)
+
+
+@pytest.mark.parametrize("tiles", [(256, 0, 0, 0), (512, 0, 0, 0), (256, 16, 4, 3), (512, 32, 8, 7),
+                                   (256, 64, 2, 5)])
+def test_tile_schedules_bitwise_identical(lb, tiles):
+    """The result does not depend on the tile schedule (catches LDS halo races
+    and ragged-tile indexing)."""
+    nx, ny, nz = 70, 23, 19
+    f0 = li.random_populations(nx, ny, nz, seed=3, base_a=0.3, base_b=0.4, amp=0.05)
+    ref = lb.Sim(lb.make_params(nx, ny, nz, psi="exp", g=2.0, sink="faces", rho_h=0.03))
+    ref.init_from_populations(f0)
+    ref.step(7)
+    sim = lb.Sim(lb.make_params(nx, ny, nz, psi="exp", g=2.0, sink="faces", rho_h=0.03))
+    sim.set_tiles(*tiles)
+    sim.init_from_populations(f0)
+    sim.step(7)
+    assert torch.equal(sim.populations(), ref.populations())
+
+
+def test_batched_instances_equal_separate_runs(lb):
+    shapes = [(24, 24, 24, 0.85, 0.03), (40, 40, 40, 0.97, 0.05), (17, 21, 13, 0.9, 0.02)]
+    params = [lb.make_params(n0, n1, n2, g=g, sink="faces", rho_h=rh, precision="fp32s")
+              for n0, n1, n2, g, rh in shapes]
+    batch = lb.Sim(params)
+    singles = []
+    for k, (n0, n1, n2, g, rh) in enumerate(shapes):
+        a, b = li.droplet(n0, n1, n2, 0.2 * n0)
+        batch.init_from_density(a, b, inst=k)
+        s = lb.Sim(params[k])
+        s.init_from_density(a, b)
+        singles.append(s)
+    batch.step(25)
+    for k, s in enumerate(singles):
+        s.step(25)
+        assert torch.equal(batch.populations(inst=k), s.populations())
+        db, ds = batch.diagnostics(inst=k), s.diagnostics()
+        assert db["mass"] == ds["mass"] and db["evaporated"] == ds["evaporated"]
+
+
+def test_graph_replay_and_checkpoint_bitwise(lb):
+    nx, ny, nz = 32, 30, 28
+    p = lb.make_params(nx, ny, nz, g=0.9, sink="faces", rho_h=0.03, precision="fp32s")
+    a, b = li.droplet(nx, ny, nz, 7.0)
+    ref = lb.Sim(p)
+    ref.init_from_density(a, b)
+    ref.step(41)
+    g = lb.Sim(p)
+    g.set_graph(8)
+    g.init_from_density(a, b)
+    g.step(17)
+    blob = g.checkpoint()
+    g.step(24)
+    assert torch.equal(g.populations(), ref.populations())
+    r = lb.Sim(p)
+    r.init_from_density(a, a)  # different state, overwritten by the restore
+    r.restore(blob)
+    r.step(24)
+    assert torch.equal(r.populations(), ref.populations())
+    dr, dref = r.diagnostics(), ref.diagnostics()
+    assert dr["step"] == dref["step"] == 41
+    assert abs(dr["evaporated"] - dref["evaporated"]) < 1e-12
+
+
+@pytest.mark.parametrize("precision,tol_rho", [("fp32s", 1e-5), ("fp16s", 1e-3)])
+def test_reduced_precision_film_against_oracle(lb, precision, tol_rho):
+    w = li.film_small()
+    sim, orc = _pair(lb, w.nx, w.ny, w.nz, precision=precision, psi=w.psi, g=w.g, sink=w.sink, wall_z=w.wall_z,
+                     rho_h=w.rho_h)
+    a, b = w.densities()
+    sim.init_from_density(a, b)
+    orc.init_from_density(a, b)
+    sim.step(w.steps)
+    orc.step(w.steps)
+    ra = sim.density(0).cpu().numpy()
+    ora, orb = orc.density()
+    err = np.max(np.abs(ra - ora))
+    assert err < tol_rho, err
+    dg, do = sim.diagnostics(), orc.diagnostics()
+    tot = do["mass"][0] + do["mass"][1]
+    drift = abs(dg["mass"][0] + dg["mass"][1] - tot) / tot
+    assert drift < (1e-6 if precision == "fp32s" else 1e-3), drift
+    assert abs(dg["z_interface"] - do["z_interface"]) < (0.01 if precision == "fp32s" else 0.1)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32s", 2e-6), ("fp16s", 2e-3)])
+def test_reduced_precision_droplet_against_oracle(lb, precision, tol):
+    nx = ny = nz = 40
+    sim, orc = _pair(lb, nx, ny, nz, precision=precision, g=0.9, sink="faces", rho_h=0.04)
+    a, b = li.droplet(nx, ny, nz, 8.0)
+    sim.init_from_density(a, b)
+    orc.init_from_density(a, b)
+    sim.step(50)
+    orc.step(50)
+    got = sim.density(0).cpu().numpy()
+    ref = orc.density()[0]
+    assert np.max(np.abs(got - ref)) < tol * 10
+    dg, do = sim.diagnostics(), orc.diagnostics()
+    tot = do["mass"][0] + do["mass"][1]
+    assert abs(dg["mass"][0] + dg["evaporated"] - (do["mass"][0] + do["evaporated"])) / tot < tol
