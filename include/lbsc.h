@@ -72,7 +72,8 @@ enum { LBSC_PSI_RHO = 0, LBSC_PSI_EXP = 1 };
 enum { LBSC_SINK_NONE = 0, LBSC_SINK_ZMAX = 1, LBSC_SINK_FACES = 2, LBSC_SINK_SPHERE = 3 };
 
 typedef struct lbsc_params {
-    int32_t nx, ny, nz;      /* lattice size, each 1..4096, nx*ny*nz < 2^31 */
+    int32_t nx, ny, nz;      /* lattice size, each 1..4096, nx*ny*nz < 2^31 and
+                                nx*ny*nz*element size < 4 GiB */
     int32_t wall_z;          /* 1: half-way bounce-back wall on the z seam */
     double tau[2];           /* relaxation times tau^A, tau^B (> 0.5) */
     double g;                /* interaction strength g^{AB} = g^{BA} */

@@ -48,17 +48,57 @@ struct NodeVals {
     A rho[2];
 };
 
+// Source node of the pull of direction i, as a 32-bit index, given the
+// wrapped neighbour coordinates. Every (c, i) plane is addressed from its own
+// block-uniform base pointer, so each load needs one 32-bit offset register.
+struct Nbr {
+    uint32_t xs[3];   // x - 1, x, x + 1 (wrapped)
+    uint32_t ys[3];   // row offsets (y - 1, y, y + 1 wrapped) * nx
+    uint32_t zs[3];   // plane offsets (z - 1, z, z + 1 wrapped) * nx * ny
+    uint32_t self;
+};
+
+__device__ __forceinline__ Nbr neighbours(int x, int y, int z, int nx, int ny, int nz)
+{
+    Nbr n;
+    n.xs[0] = (uint32_t)wrap(x - 1, nx); n.xs[1] = (uint32_t)x; n.xs[2] = (uint32_t)wrap(x + 1, nx);
+    n.ys[0] = (uint32_t)wrap(y - 1, ny) * nx; n.ys[1] = (uint32_t)y * nx; n.ys[2] = (uint32_t)wrap(y + 1, ny) * nx;
+    const uint32_t pl = (uint32_t)nx * (uint32_t)ny;
+    n.zs[0] = (uint32_t)wrap(z - 1, nz) * pl; n.zs[1] = (uint32_t)z * pl; n.zs[2] = (uint32_t)wrap(z + 1, nz) * pl;
+    n.self = n.zs[1] + n.ys[1] + n.xs[1];
+    return n;
+}
+
+// Element `node` of a plane whose base is block-uniform, addressed by a
+// 32-bit byte offset (planes are < 4 GiB) so the load can take its base from
+// scalar registers.
+template <typename T>
+__device__ __forceinline__ T ldp(const T* __restrict__ plane, uint32_t node)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(plane) + (uint32_t)(node * (uint32_t)sizeof(T)));
+}
+
+template <typename T>
+__device__ __forceinline__ void stp(T* __restrict__ plane, uint32_t node, T v)
+{
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + (uint32_t)(node * (uint32_t)sizeof(T))) = v;
+}
+
 template <typename T, typename A>
 __device__ __forceinline__ void pull_node(const T* __restrict__ src, const Inst& I, int x, int y, int z,
                                           NodeVals<T, A>& v)
 {
+    const Nbr nb = neighbours(x, y, z, I.nx, I.ny, I.nz);
+    // z is uniform over the block for every call, so the wall branch is too.
+    const bool wall_lo = I.wall_z && z == 0, wall_hi = I.wall_z && z == I.nz - 1;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-        PullSrc s = pull_src(i, x, y, z, I.nx, I.ny, I.nz, I.wall_z);
-        const int q = s.reflected ? opp(i) : i;
-        const int64_t node = node_of(s.x, s.y, s.z, I.nx, I.ny);
-        v.f[0][i] = (A)src[(int64_t)q * I.pstride + node];
-        v.f[1][i] = (A)src[(int64_t)(kQ + q) * I.pstride + node];
+        // pull from x - e_i
+        const bool refl = (ez(i) > 0 && wall_lo) || (ez(i) < 0 && wall_hi);
+        const int q = refl ? opp(i) : i;
+        const uint32_t node = refl ? nb.self : nb.zs[1 - ez(i)] + nb.ys[1 - ey(i)] + nb.xs[1 - ex(i)];
+        v.f[0][i] = (A)ldp(src + (int64_t)q * I.pstride, node);
+        v.f[1][i] = (A)ldp(src + (int64_t)(kQ + q) * I.pstride, node);
     }
 }
 
@@ -210,19 +250,9 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
     NodeVals<T, A> cur, nxt;
 
     // Pull plane zq (logical z) into LDS slot sl; tile nodes keep their values.
+    // Halo nodes first, so only one extra population set is live at a time.
     auto load_plane = [&](int zq, int sl, NodeVals<T, A>& keep) {
         const int zp = psi_plane(zq, I.nz, I.wall_z);
-        if (own) {
-            pull_node<T, A>(s, I, x, y, zp, keep);
-            node_density<T, A>(I, keep);
-            if (in_sink(I.reset, x, y, zp, I.nx, I.ny, I.nz)) {
-                const double fl = sink_reset<T, A>(I, keep);
-                if (book && zq >= z0 && zq < z1) eflux += fl;
-            }
-            const int fi = (ty + 1) * row + tx + 1;
-            psiS[sl][0][fi] = psi_of<A>(keep.rho[0], I.psi_exp);
-            psiS[sl][1][fi] = psi_of<A>(keep.rho[1], I.psi_exp);
-        }
         for (int r = t; r < nring; r += NT) {
             int fx, fy;
             ring_coord(r, tw, th, fx, fy);
@@ -235,13 +265,24 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
             psiS[sl][0][fi] = psi_of<A>(h.rho[0], I.psi_exp);
             psiS[sl][1][fi] = psi_of<A>(h.rho[1], I.psi_exp);
         }
+        if (own) {
+            pull_node<T, A>(s, I, x, y, zp, keep);
+            node_density<T, A>(I, keep);
+            if (in_sink(I.reset, x, y, zp, I.nx, I.ny, I.nz)) {
+                const double fl = sink_reset<T, A>(I, keep);
+                if (book && zq >= z0 && zq < z1) eflux += fl;
+            }
+            const int fi = (ty + 1) * row + tx + 1;
+            psiS[sl][0][fi] = psi_of<A>(keep.rho[0], I.psi_exp);
+            psiS[sl][1][fi] = psi_of<A>(keep.rho[1], I.psi_exp);
+        }
     };
 
     // Collide plane z of the tile node held in v and store f* to dst.
     auto collide_plane = [&](int z, NodeVals<T, A>& v) {
         if (!own) return;
         const int sm = (z - z0) % 3, s0 = (z - z0 + 1) % 3, sp = (z - z0 + 2) % 3;
-        const int64_t node = node_of(x, y, z, I.nx, I.ny);
+        const uint32_t node = ((uint32_t)z * (uint32_t)I.ny + (uint32_t)y) * (uint32_t)I.nx + (uint32_t)x;
         if (!in_sink(I.cur, x, y, z, I.nx, I.ny, I.nz)) {
             A S[2][3] = {{0, 0, 0}, {0, 0, 0}};
 #pragma unroll
@@ -262,8 +303,8 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
         }
 #pragma unroll
         for (int i = 0; i < kQ; ++i) {
-            d[(int64_t)i * I.pstride + node] = (T)v.f[0][i];
-            d[(int64_t)(kQ + i) * I.pstride + node] = (T)v.f[1][i];
+            stp(d + (int64_t)i * I.pstride, node, (T)v.f[0][i]);
+            stp(d + (int64_t)(kQ + i) * I.pstride, node, (T)v.f[1][i]);
         }
     };
 

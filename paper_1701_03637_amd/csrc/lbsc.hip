@@ -119,6 +119,8 @@ lbsc_status validate(const lbsc_params& p, int k, std::string& why)
     };
     if (p.nx < 1 || p.ny < 1 || p.nz < 1 || p.nx > 4096 || p.ny > 4096 || p.nz > 4096) return bad("size out of 1..4096");
     if ((int64_t)p.nx * p.ny * p.nz >= (int64_t(1) << 31)) return bad("nx*ny*nz must be < 2^31");
+    if ((int64_t)p.nx * p.ny * p.nz * (int64_t)elem_size(p.precision) >= (int64_t(1) << 32))
+        return bad("one population plane must be < 4 GiB");
     if (!(p.tau[0] > 0.5) || !(p.tau[1] > 0.5)) return bad("tau must be > 0.5");
     if (!std::isfinite(p.g)) return bad("g not finite");
     if (p.psi != LBSC_PSI_RHO && p.psi != LBSC_PSI_EXP) return bad("unknown psi");
@@ -580,9 +582,11 @@ lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
     if (s) return s;
     if (steps < 2) return fail(c, LBSC_E_ARG, "tune: steps must be >= 2");
     std::vector<lbsc_tiles> cands;
-    for (int nt : {256, 512})
-        for (int tw : {0, 32, 64, 128})
-            for (int nzc : {0, 8, 16, 32, 64}) cands.push_back(lbsc_tiles{nt, tw, 0, nzc});
+    for (int nt : {256, 512}) {
+        if (nt == 512 && c->precision == LBSC_FP64) continue;  // 512 x FP64 exceeds the register file
+        for (int tw : {0, 16, 32, 64})
+            for (int nzc : {0, 4, 8, 16, 32, 64, 4096}) cands.push_back(lbsc_tiles{nt, tw, 0, nzc});
+    }
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
