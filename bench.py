@@ -84,9 +84,14 @@ def timed_run(sim, steps, warmup, diag_every, torch):
     return wall_ms, step_ms, diag
 
 
-def form_single(lb, torch, w, precision, steps, warmup, diag_every, graph):
+def form_single(lb, torch, w, precision, steps, warmup, diag_every, graph, tune_steps):
     sim = make_sim(lb, w, precision)
     a, b = w.densities()
+    tiles = None
+    if tune_steps:
+        # the tuner advances the state, so initialise again afterwards
+        sim.init_from_density(a, b)
+        tiles = sim.tune(tune_steps)
     sim.init_from_density(a, b)
     d0 = sim.diagnostics()
     if graph:
@@ -106,6 +111,7 @@ def form_single(lb, torch, w, precision, steps, warmup, diag_every, graph):
         "r_droplet": d1["r_droplet"],
         "evaporated": d1["evaporated"],
         "items_per_step": sim.num_items(),
+        "tiles": tiles,
     }
     out["hbm_frac_alg"] = out["alg_GBps"] / HBM_PEAK_GBPS
     rho = sim.density(0)
@@ -113,14 +119,19 @@ def form_single(lb, torch, w, precision, steps, warmup, diag_every, graph):
     return out, rho
 
 
-def form_batched(lb, torch, steps, warmup, diag_every):
+def form_batched(lb, torch, steps, warmup, diag_every, tune_steps):
     import lbinputs as li
     ws = li.batch64()
     params = [lb.make_params(w.nx, w.ny, w.nz, g=w.g, psi=w.psi, precision="fp32s", sink=w.sink, rho_h=w.rho_h)
               for w in ws]
     sim = lb.Sim(params)
-    for k, w in enumerate(ws):
-        a, b = w.densities()
+    dens = [w.densities() for w in ws]
+    tiles = None
+    if tune_steps:
+        for k, (a, b) in enumerate(dens):
+            sim.init_from_density(a, b, inst=k)
+        tiles = sim.tune(tune_steps)
+    for k, (a, b) in enumerate(dens):
         sim.init_from_density(a, b, inst=k)
     nodes = sum(w.nodes for w in ws)
     m0 = []
@@ -148,6 +159,7 @@ def form_batched(lb, torch, steps, warmup, diag_every):
         "kernel_ms_per_step": step_ms / steps,
         "alg_GBps": nodes * 304 / (step_ms / steps * 1e-3) / 1e9,
         "items_per_step": sim.num_items(),
+        "tiles": tiles,
         "max_mass_drift_rel": drift,
     }
     res["hbm_frac_alg"] = res["alg_GBps"] / HBM_PEAK_GBPS
@@ -155,15 +167,17 @@ def form_batched(lb, torch, steps, warmup, diag_every):
     return res
 
 
-def copy_ceiling(torch, nbytes=2 << 30):
-    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+def copy_ceiling(lb, torch, nbytes=2 << 30):
+    """Read + write GB/s of the library's streaming copy kernel over 2 GiB."""
+    from paper_1701_03637_amd.lbsc import stream_copy
+    src = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
+    stream_copy(dst, src)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
     for _ in range(10):
-        dst.copy_(src)
+        stream_copy(dst, src)
     ev1.record()
     torch.cuda.synchronize()
     gbps = 2 * nbytes * 10 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
@@ -194,6 +208,7 @@ def main():
     ap.add_argument("--forms", default="fp64,fp16s,batched,large",
                     help="extra forms besides the fp32s headline (comma list, or 'none')")
     ap.add_argument("--graph", type=int, default=0, help="steps per HIP graph (0: direct launches)")
+    ap.add_argument("--tune-steps", type=int, default=20, help="steps per candidate of the tile tuner (0: defaults)")
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -211,17 +226,20 @@ def main():
     forms = [f for f in args.forms.split(",") if f and f != "none"]
 
     w = li.droplet_128()
-    head, rho32 = form_single(lb, torch, w, "fp32s", args.steps, args.warmup, args.diag_every, args.graph)
+    head, rho32 = form_single(lb, torch, w, "fp32s", args.steps, args.warmup, args.diag_every, args.graph,
+                              args.tune_steps)
     print(f"# fp32s {head['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     extra = {}
     if "fp64" in forms:
-        f64, rho64 = form_single(lb, torch, w, "fp64", args.steps, args.warmup, args.diag_every, args.graph)
+        f64, rho64 = form_single(lb, torch, w, "fp64", args.steps, args.warmup, args.diag_every, args.graph,
+                                 args.tune_steps)
         head["max_abs_drho_vs_fp64"] = float((rho32 - rho64).abs().max())
         head["speedup_vs_fp64"] = head["mlups"] / f64["mlups"]
         extra["fp64"] = f64
         print(f"# fp64 {f64['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         if "fp16s" in forms:
-            f16, rho16 = form_single(lb, torch, w, "fp16s", args.steps, args.warmup, args.diag_every, args.graph)
+            f16, rho16 = form_single(lb, torch, w, "fp16s", args.steps, args.warmup, args.diag_every,
+                                     args.graph, args.tune_steps)
             f16["max_abs_drho_vs_fp64"] = float((rho16 - rho64).abs().max())
             f16["speedup_vs_fp64"] = f16["mlups"] / f64["mlups"]
             extra["fp16s"] = f16
@@ -231,17 +249,19 @@ def main():
     del rho32
     torch.cuda.empty_cache()
     if "batched" in forms:
-        extra["batched"] = form_batched(lb, torch, max(args.steps // 20, 10), 20, args.diag_every)
+        extra["batched"] = form_batched(lb, torch, max(args.steps // 20, 10), 20, args.diag_every,
+                                        min(args.tune_steps, 5))
         print(f"# batched {extra['batched']['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     if "large" in forms:
         wl = li.droplet_512()
-        big, rho = form_single(lb, torch, wl, "fp32s", max(args.steps // 40, 10), 20, 0, args.graph)
+        big, rho = form_single(lb, torch, wl, "fp32s", max(args.steps // 40, 10), 20, 0, args.graph,
+                               min(args.tune_steps, 5))
         del rho
         extra["large"] = big
         print(f"# large {big['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
-    ceiling = copy_ceiling(torch)
+    ceiling = copy_ceiling(lb, torch)
 
     kms = head["kernel_ms_per_step"]
     achieved = w.nodes * BYTES_PER_LU["fp32s"] / (kms * 1e-3) / 1e9
@@ -262,11 +282,11 @@ def main():
         "config": {"workload": "droplet_128^3 radius 24, psi=rho, g=0.9, tau=1, sink rho_H=0.04 on 6 faces, "
                                "FP32-shifted storage (rho0 = 0.04, 0.70), FP64 diagnostics every "
                                f"{args.diag_every} steps", "nodes": w.nodes, "precision": "fp32s",
-                   "graph_steps": args.graph},
+                   "graph_steps": args.graph, "tiles": head["tiles"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic,
-                     "kernel": "lbsc::k_step<float,256>", "alg_bytes_per_launch": w.nodes * BYTES_PER_LU["fp32s"],
+                     "kernel": "lbsc::k_step<float,...>", "alg_bytes_per_launch": w.nodes * BYTES_PER_LU["fp32s"],
                      "avg_launch_ms": kms},
         "copy_ceiling_GBps": ceiling,
         "headline": head,

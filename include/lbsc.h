@@ -73,7 +73,7 @@ enum { LBSC_SINK_NONE = 0, LBSC_SINK_ZMAX = 1, LBSC_SINK_FACES = 2, LBSC_SINK_SP
 
 typedef struct lbsc_params {
     int32_t nx, ny, nz;      /* lattice size, each 1..4096, nx*ny*nz < 2^31 and
-                                nx*ny*nz*element size < 4 GiB */
+                                38*nx*ny*element size < 4 GiB */
     int32_t wall_z;          /* 1: half-way bounce-back wall on the z seam */
     double tau[2];           /* relaxation times tau^A, tau^B (> 0.5) */
     double g;                /* interaction strength g^{AB} = g^{BA} */
@@ -81,7 +81,9 @@ typedef struct lbsc_params {
     int32_t precision;       /* LBSC_FP64/FP32S/FP16S; equal for all instances */
     double shift[2];         /* rho0^c of shifted storage (ignored for FP64) */
     int32_t sink;            /* LBSC_SINK_* */
-    int32_t reserved;
+    int32_t plane_pad;       /* extra elements between population planes
+                                (>= 0; spreads the 38 plane streams over HBM
+                                channels); 0 = none */
     double rho_h;            /* density imposed on A at sink nodes */
     double sink_radius;      /* LBSC_SINK_SPHERE only */
     double center[3];        /* sphere centre (x, y, z) in node units */
@@ -108,10 +110,13 @@ typedef struct lbsc_diag {
 typedef struct lbsc_ctx lbsc_ctx;
 
 /* Tile schedule of the fused step kernel: nt threads per block (256 or 512),
- * xy tile tw x th (tw, th <= 128, tw*th <= nt), z chunk of nzc planes. Zero
- * or negative fields mean "choose automatically". */
+ * xy tile tw x th (tw, th <= 128, tw*th <= nt), z chunk of nzc planes, and the
+ * kernel variant: 1 keeps a node's pulled populations in registers from its
+ * density pass to its collision, 2 pulls the node again for the collision
+ * (fewer registers, more blocks per CU). Zero or negative fields mean "choose
+ * automatically". */
 typedef struct lbsc_tiles {
-    int32_t nt, tw, th, nzc;
+    int32_t nt, tw, th, nzc, variant;
 } lbsc_tiles;
 
 /* Static description of a status code. */
@@ -181,6 +186,11 @@ lbsc_status lbsc_diagnostics(lbsc_ctx* ctx, int32_t inst, lbsc_diag* out);
 lbsc_status lbsc_checkpoint_bytes(const lbsc_ctx* ctx, size_t* bytes);
 lbsc_status lbsc_save(lbsc_ctx* ctx, void* blob_dev);
 lbsc_status lbsc_load(lbsc_ctx* ctx, const void* blob_dev);
+
+/* Copies `bytes` (a multiple of 16, 16-byte aligned pointers) from src to dst
+ * on the given stream with a plain streaming kernel: the HBM bandwidth ceiling
+ * the step kernel is measured against, and the calibration of byte counters. */
+lbsc_status lbsc_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
 
 /* Host-only checks of the index geometry (no GPU needed); 0 on success,
  * otherwise the number of failed checks. */

@@ -3,8 +3,10 @@
 // arXiv:1701.03637, Sec. II), written for gfx950 (wave64, no MFMA: the step
 // is a memory-bound stencil, not a contraction).
 //
-// Storage. The populations of one instance live in an SoA arena:
-//   arena[base + (c*19 + i)*pstride + node],  node = (z*ny + y)*nx + x.
+// Storage. The populations of one instance live in a z-slab-major SoA arena:
+//   arena[base + z*slab + (c*19 + i)*ps + y*nx + x],  slab = 38*ps,
+// so the 38 population planes of one z-plane are contiguous and a pull needs
+// only the three slab bases z-1, z, z+1 plus a 32-bit offset per lane.
 // The stored buffer holds post-collision populations f*(t-1); the state S(t)
 // of the method (post-stream, post-sink) is obtained by pulling,
 //   f_i(x) = f*_i(x - e_i), or f*_opp(i)(x) across a z-seam wall,
@@ -45,60 +47,74 @@ template <> __device__ __forceinline__ float psi_of<float>(float rho, int psi_ex
 template <typename T, typename A>
 struct NodeVals {
     A f[2][kQ];
-    A rho[2];
+    A rho[2];    // rho0 + drho
+    A drho[2];   // sum of the stored deviations
 };
 
-// Source node of the pull of direction i, as a 32-bit index, given the
-// wrapped neighbour coordinates. Every (c, i) plane is addressed from its own
-// block-uniform base pointer, so each load needs one 32-bit offset register.
-struct Nbr {
-    uint32_t xs[3];   // x - 1, x, x + 1 (wrapped)
-    uint32_t ys[3];   // row offsets (y - 1, y, y + 1 wrapped) * nx
-    uint32_t zs[3];   // plane offsets (z - 1, z, z + 1 wrapped) * nx * ny
-    uint32_t self;
-};
+// Populations are read and written with raw buffer instructions: the
+// resource (4 scalar registers) points at one z-slab, the plane offset
+// (c*19 + i)*ps*sizeof(T) is a scalar offset and the in-plane offset a single
+// vector register shared by both components and all planes. A slab is below
+// 4 GiB (checked at create), so no access is clipped.
+using Rsrc = __amdgpu_buffer_rsrc_t;
 
-__device__ __forceinline__ Nbr neighbours(int x, int y, int z, int nx, int ny, int nz)
+__device__ __forceinline__ Rsrc slab_rsrc(const void* p)
 {
-    Nbr n;
-    n.xs[0] = (uint32_t)wrap(x - 1, nx); n.xs[1] = (uint32_t)x; n.xs[2] = (uint32_t)wrap(x + 1, nx);
-    n.ys[0] = (uint32_t)wrap(y - 1, ny) * nx; n.ys[1] = (uint32_t)y * nx; n.ys[2] = (uint32_t)wrap(y + 1, ny) * nx;
-    const uint32_t pl = (uint32_t)nx * (uint32_t)ny;
-    n.zs[0] = (uint32_t)wrap(z - 1, nz) * pl; n.zs[1] = (uint32_t)z * pl; n.zs[2] = (uint32_t)wrap(z + 1, nz) * pl;
-    n.self = n.zs[1] + n.ys[1] + n.xs[1];
-    return n;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, -1, 0x00020000);
 }
 
-// Element `node` of a plane whose base is block-uniform, addressed by a
-// 32-bit byte offset (planes are < 4 GiB) so the load can take its base from
-// scalar registers.
-template <typename T>
-__device__ __forceinline__ T ldp(const T* __restrict__ plane, uint32_t node)
+template <typename T> __device__ __forceinline__ T bload(Rsrc r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ float bload<float>(Rsrc r, uint32_t voff, uint32_t soff)
 {
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(plane) + (uint32_t)(node * (uint32_t)sizeof(T)));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <> __device__ __forceinline__ double bload<double>(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+template <> __device__ __forceinline__ _Float16 bload<_Float16>(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(_Float16, (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0));
 }
 
-template <typename T>
-__device__ __forceinline__ void stp(T* __restrict__ plane, uint32_t node, T v)
+__device__ __forceinline__ void bstore(float v, Rsrc r, uint32_t voff, uint32_t soff)
 {
-    *reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + (uint32_t)(node * (uint32_t)sizeof(T))) = v;
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bstore(double v, Rsrc r, uint32_t voff, uint32_t soff)
+{
+    using U2 = unsigned int __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bstore(_Float16 v, Rsrc r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)voff, (int)soff, 0);
 }
 
 template <typename T, typename A>
 __device__ __forceinline__ void pull_node(const T* __restrict__ src, const Inst& I, int x, int y, int z,
                                           NodeVals<T, A>& v)
 {
-    const Nbr nb = neighbours(x, y, z, I.nx, I.ny, I.nz);
-    // z is uniform over the block for every call, so the wall branch is too.
-    const bool wall_lo = I.wall_z && z == 0, wall_hi = I.wall_z && z == I.nz - 1;
+    const int nx = I.nx, ny = I.ny, nz = I.nz;
+    constexpr uint32_t E = sizeof(T);
+    const uint32_t xs[3] = {(uint32_t)wrap(x - 1, nx) * E, (uint32_t)x * E, (uint32_t)wrap(x + 1, nx) * E};
+    const uint32_t ys[3] = {(uint32_t)(wrap(y - 1, ny) * nx) * E, (uint32_t)(y * nx) * E,
+                            (uint32_t)(wrap(y + 1, ny) * nx) * E};
+    // z is block-uniform for every call, so the resources and the wall
+    // branch are scalar.
+    const bool wall_lo = I.wall_z && z == 0, wall_hi = I.wall_z && z == nz - 1;
+    const Rsrc sl[3] = {slab_rsrc(src + (int64_t)wrap(z - 1, nz) * I.slab), slab_rsrc(src + (int64_t)z * I.slab),
+                        slab_rsrc(src + (int64_t)wrap(z + 1, nz) * I.slab)};
+    const uint32_t psb = (uint32_t)I.ps * E;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-        // pull from x - e_i
+        // pull from x - e_i, or the reflected population across a wall
         const bool refl = (ez(i) > 0 && wall_lo) || (ez(i) < 0 && wall_hi);
         const int q = refl ? opp(i) : i;
-        const uint32_t node = refl ? nb.self : nb.zs[1 - ez(i)] + nb.ys[1 - ey(i)] + nb.xs[1 - ex(i)];
-        v.f[0][i] = (A)ldp(src + (int64_t)q * I.pstride, node);
-        v.f[1][i] = (A)ldp(src + (int64_t)(kQ + q) * I.pstride, node);
+        const Rsrc r = refl ? sl[1] : sl[1 - ez(i)];
+        const uint32_t xy = refl ? ys[1] + xs[1] : ys[1 - ey(i)] + xs[1 - ex(i)];
+        v.f[0][i] = (A)bload<T>(r, xy, (uint32_t)q * psb);
+        v.f[1][i] = (A)bload<T>(r, xy, (uint32_t)(kQ + q) * psb);
     }
 }
 
@@ -107,11 +123,27 @@ __device__ __forceinline__ void node_density(const Inst& I, NodeVals<T, A>& v)
 {
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-        A r = (A)I.shift[c];
+        A r = (A)0;
 #pragma unroll
         for (int i = 0; i < kQ; ++i) r += v.f[c][i];
-        v.rho[c] = r;
+        v.drho[c] = r;
+        v.rho[c] = (A)I.shift[c] + r;
     }
+}
+
+// FP64 arithmetic follows the plain formulas; FP32 arithmetic moves every
+// rounding of a mass-conserving update into the rest population, so that the
+// stored deviations of a node sum exactly (up to one rounding) to its density.
+template <typename A> constexpr bool kPlain = false;
+template <> constexpr bool kPlain<double> = true;
+
+template <typename A>
+__device__ __forceinline__ void absorb_rest(A (&f)[kQ], A total)
+{
+    A moving = (A)0;
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) moving += f[i];
+    f[0] = total - moving;
 }
 
 // Sink reset (Sec. II C): A -> f^eq(rho_H, 0), B -> f^eq(rhoA + rhoB - rho_H, 0)
@@ -120,14 +152,22 @@ template <typename T, typename A>
 __device__ __forceinline__ double sink_reset(const Inst& I, NodeVals<T, A>& v)
 {
     const double rho_h = I.reset.rho_h;
-    const double flux = (double)v.rho[0] - rho_h;
-    const A rbh = v.rho[0] + v.rho[1] - (A)rho_h;
+    const double flux = I.shift[0] + (double)v.drho[0] - rho_h;
+    // rho_H - rho0^A is exact in FP64; the partner deviation
+    // rhoB_H - rho0^B = (rho0^A - rho_H) + drho^A + drho^B is formed from
+    // small terms, so no O(1) density is rounded.
     const A da = (A)(rho_h - I.shift[0]);
-    const A db = rbh - (A)I.shift[1];
+    const A db = (A)(I.shift[0] - rho_h) + v.drho[0] + v.drho[1];
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
         v.f[0][i] = (A)wgt(i) * da;
         v.f[1][i] = (A)wgt(i) * db;
+    }
+    if constexpr (!kPlain<A>) {
+        // FP32 weights do not sum to 1 exactly; the rest population takes
+        // the residual so each component holds exactly its reset density.
+        absorb_rest(v.f[0], da);
+        absorb_rest(v.f[1], db);
     }
     node_density<T, A>(I, v);
     return flux;
@@ -153,30 +193,35 @@ __device__ __forceinline__ void collide_node(const Inst& I, NodeVals<T, A>& v, c
         }
         j[c][0] = jx; j[c][1] = jy; j[c][2] = jz;
     }
-    const A rt = v.rho[0] + v.rho[1];
-    const A up[3] = {(j[0][0] + j[1][0]) / rt, (j[0][1] + j[1][1]) / rt, (j[0][2] + j[1][2]) / rt};
+    // u' = sum_c j^c / sum_c rho^c; the force shift tau^c F^c / rho^c with
+    // F^c = -psi^c g S^c is applied as u^c = u' + k^c S^c.
+    const A inv_rt = (A)1 / (v.rho[0] + v.rho[1]);
+    const A up[3] = {(j[0][0] + j[1][0]) * inv_rt, (j[0][1] + j[1][1]) * inv_rt, (j[0][2] + j[1][2]) * inv_rt};
     const A psi[2] = {psiA, psiB};
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const A tau = (A)I.tau[c];
-        const A g = (A)I.g;
-        A u[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const A F = -psi[c] * g * S[c][d];
-            u[d] = up[d] + (v.rho[c] != (A)0 ? tau * F / v.rho[c] : (A)0);
-        }
-        const A uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
         const A rho = v.rho[c];
-        const A drho = rho - (A)I.shift[c];
+        const A kc = rho != (A)0 ? -tau * (A)I.g * psi[c] / rho : (A)0;
+        const A u[3] = {up[0] + kc * S[c][0], up[1] + kc * S[c][1], up[2] + kc * S[c][2]};
+        const A uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        const A drho = v.drho[c];
         const A omega = (A)1 / tau;
+        // Rest: f^eq_0 = w_0 (drho + rho (-1.5 u.u)) in deviation form.
+        const A base0 = drho - (A)1.5 * rho * uu;
+        v.f[c][0] = v.f[c][0] - (v.f[c][0] - (A)wgt(0) * base0) * omega;
+        // Opposite pairs (i, i+1) share w, |e.u| and the even part of q.
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) {
+        for (int i = 1; i < kQ; i += 2) {
             const A eu = (A)ex(i) * u[0] + (A)ey(i) * u[1] + (A)ez(i) * u[2];
-            const A q = (A)3 * eu + (A)4.5 * eu * eu - (A)1.5 * uu;
-            const A feq = (A)wgt(i) * (drho + rho * q);
-            v.f[c][i] = v.f[c][i] - (v.f[c][i] - feq) * omega;
+            const A even = (A)wgt(i) * (base0 + (A)4.5 * rho * eu * eu);
+            const A odd = (A)wgt(i) * (A)3 * rho * eu;
+            const A fp = even + odd, fm = even - odd;
+            v.f[c][i] = v.f[c][i] - (v.f[c][i] - fp) * omega;
+            v.f[c][i + 1] = v.f[c][i + 1] - (v.f[c][i + 1] - fm) * omega;
         }
+        // BGK conserves each component's mass exactly (sum_i f^eq_i = rho).
+        if constexpr (!kPlain<A>) absorb_rest(v.f[c], drho);
     }
 }
 
@@ -185,8 +230,10 @@ __device__ __forceinline__ void collide_node(const Inst& I, NodeVals<T, A>& v, c
 // ---------------------------------------------------------------------------
 
 template <int NT> struct Foot {
-    // Largest (tw + 2)(th + 2) over tiles with tw * th <= NT, tw, th <= 128.
-    static constexpr int kMax = NT + 2 * (128 + 128) + 4;
+    // Largest (tw + 2)(th + 2) = tw*th + 2(tw + th) + 4 over tiles with
+    // tw*th <= NT and tw, th <= min(NT, 128): tw + th peaks at the extremes.
+    static constexpr int kSide = NT < 128 ? NT : 128;
+    static constexpr int kMax = NT + 2 * (kSide + NT / kSide) + 4;
 };
 
 __device__ __forceinline__ void ring_coord(int r, int tw, int th, int& fx, int& fy)
@@ -217,7 +264,11 @@ __device__ __forceinline__ A block_sum_wave(A v)
     return v;
 }
 
-template <typename T, int NT>
+// KEEP = true: a tile node's pulled populations stay in registers from the
+// plane-ahead density pass to its collision (two population sets live).
+// KEEP = false: the density pass keeps only the densities and the collision
+// pulls the node again (one set live, higher occupancy, second read from L2).
+template <typename T, int NT, bool KEEP>
 __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, const Item* __restrict__ items,
                                              int n_items, const T* __restrict__ src, T* __restrict__ dst,
                                              double* __restrict__ eacc)
@@ -251,7 +302,7 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
 
     // Pull plane zq (logical z) into LDS slot sl; tile nodes keep their values.
     // Halo nodes first, so only one extra population set is live at a time.
-    auto load_plane = [&](int zq, int sl, NodeVals<T, A>& keep) {
+    auto load_plane = [&](int zq, int sl, NodeVals<T, A>& keep_or_tmp) {
         const int zp = psi_plane(zq, I.nz, I.wall_z);
         for (int r = t; r < nring; r += NT) {
             int fx, fy;
@@ -266,6 +317,8 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
             psiS[sl][1][fi] = psi_of<A>(h.rho[1], I.psi_exp);
         }
         if (own) {
+            NodeVals<T, A> tmp;
+            NodeVals<T, A>& keep = KEEP ? keep_or_tmp : tmp;
             pull_node<T, A>(s, I, x, y, zp, keep);
             node_density<T, A>(I, keep);
             if (in_sink(I.reset, x, y, zp, I.nx, I.ny, I.nz)) {
@@ -279,32 +332,52 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
     };
 
     // Collide plane z of the tile node held in v and store f* to dst.
-    auto collide_plane = [&](int z, NodeVals<T, A>& v) {
+    auto collide_plane = [&](int z, NodeVals<T, A>& kept) {
         if (!own) return;
+        NodeVals<T, A> tmp;
+        NodeVals<T, A>& v = KEEP ? kept : tmp;
+        if constexpr (!KEEP) {
+            pull_node<T, A>(s, I, x, y, z, v);
+            node_density<T, A>(I, v);
+            if (in_sink(I.reset, x, y, z, I.nx, I.ny, I.nz)) sink_reset<T, A>(I, v);
+        }
         const int sm = (z - z0) % 3, s0 = (z - z0 + 1) % 3, sp = (z - z0 + 2) % 3;
-        const uint32_t node = ((uint32_t)z * (uint32_t)I.ny + (uint32_t)y) * (uint32_t)I.nx + (uint32_t)x;
+        const uint32_t xy = (uint32_t)y * (uint32_t)I.nx + (uint32_t)x;
         if (!in_sink(I.cur, x, y, z, I.nx, I.ny, I.nz)) {
-            A S[2][3] = {{0, 0, 0}, {0, 0, 0}};
+            // Neighbour sum of Eq. (sc) over opposite pairs: w_i e_i times the
+            // difference of psi across the node, axis and diagonal classes
+            // accumulated separately and weighted once.
+            A S1[2][3] = {{0, 0, 0}, {0, 0, 0}}, S2[2][3] = {{0, 0, 0}, {0, 0, 0}};
 #pragma unroll
-            for (int i = 1; i < kQ; ++i) {
-                const int sl = ez(i) < 0 ? sm : (ez(i) > 0 ? sp : s0);
-                const int fi = (ty + 1 + ey(i)) * row + tx + 1 + ex(i);
-                const A w = (A)wgt(i);
+            for (int i = 1; i < kQ; i += 2) {
+                const int slp = ez(i) < 0 ? sm : (ez(i) > 0 ? sp : s0);
+                const int slm = ez(i) > 0 ? sm : (ez(i) < 0 ? sp : s0);
+                const int fp = (ty + 1 + ey(i)) * row + tx + 1 + ex(i);
+                const int fm = (ty + 1 - ey(i)) * row + tx + 1 - ex(i);
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
-                    const A p = w * psiS[sl][1 - c][fi];
-                    if (ex(i)) S[c][0] += ex(i) > 0 ? p : -p;
-                    if (ey(i)) S[c][1] += ey(i) > 0 ? p : -p;
-                    if (ez(i)) S[c][2] += ez(i) > 0 ? p : -p;
+                    const A dpsi = psiS[slp][1 - c][fp] - psiS[slm][1 - c][fm];
+                    A(&acc)[3] = i < 7 ? S1[c] : S2[c];
+                    if (ex(i)) acc[0] += ex(i) > 0 ? dpsi : -dpsi;
+                    if (ey(i)) acc[1] += ey(i) > 0 ? dpsi : -dpsi;
+                    if (ez(i)) acc[2] += ez(i) > 0 ? dpsi : -dpsi;
                 }
             }
+            A S[2][3];
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int dd = 0; dd < 3; ++dd) S[c][dd] = (A)wgt(1) * S1[c][dd] + (A)wgt(7) * S2[c][dd];
             const int fc = (ty + 1) * row + tx + 1;
             collide_node<T, A>(I, v, S, psiS[s0][0][fc], psiS[s0][1][fc]);
         }
+        const Rsrc dz = slab_rsrc(d + (int64_t)z * I.slab);
+        const uint32_t psb = (uint32_t)I.ps * (uint32_t)sizeof(T);
+        const uint32_t xyb = xy * (uint32_t)sizeof(T);
 #pragma unroll
         for (int i = 0; i < kQ; ++i) {
-            stp(d + (int64_t)i * I.pstride, node, (T)v.f[0][i]);
-            stp(d + (int64_t)(kQ + i) * I.pstride, node, (T)v.f[1][i]);
+            bstore((T)v.f[0][i], dz, xyb, (uint32_t)i * psb);
+            bstore((T)v.f[1][i], dz, xyb, (uint32_t)(kQ + i) * psb);
         }
     };
 
@@ -362,8 +435,9 @@ __global__ void k_init_density(Inst I, const double* __restrict__ rhoA, const do
                 src = node_of(wrap(x + ex(i), I.nx), wrap(y + ey(i), I.ny), wrap(zt, I.nz), I.nx, I.ny);
             const double fa = wgt(i) * rhoA[src];
             const double fb = wgt(i) * rhoB[src];
-            d[(int64_t)i * I.pstride + k] = (T)(A)(fa - wgt(i) * I.shift[0]);
-            d[(int64_t)(kQ + i) * I.pstride + k] = (T)(A)(fb - wgt(i) * I.shift[1]);
+            const int64_t xy = k - (int64_t)z * I.nx * I.ny;
+            d[eidx(I, 0, i, z, xy)] = (T)(A)(fa - wgt(i) * I.shift[0]);
+            d[eidx(I, 1, i, z, xy)] = (T)(A)(fb - wgt(i) * I.shift[1]);
         }
     }
 }
@@ -391,9 +465,9 @@ __global__ void k_init_pops(Inst I, const double* __restrict__ f, T* __restrict_
                 src = node_of(wrap(x + ex(i), I.nx), wrap(y + ey(i), I.ny), wrap(zt, I.nz), I.nx, I.ny);
                 q = i;
             }
+            const int64_t xy = k - (int64_t)z * I.nx * I.ny;
             for (int c = 0; c < 2; ++c)
-                d[(int64_t)(c * kQ + i) * I.pstride + k] =
-                    (T)(A)(f[(int64_t)(c * kQ + q) * n + src] - wgt(i) * I.shift[c]);
+                d[eidx(I, c, i, z, xy)] = (T)(A)(f[(int64_t)(c * kQ + q) * n + src] - wgt(i) * I.shift[c]);
         }
     }
 }
@@ -422,8 +496,8 @@ __global__ void k_read_density(Inst I, const T* __restrict__ src, double* __rest
         const int x = (int)(k % I.nx), y = (int)((k / I.nx) % I.ny), z = (int)(k / ((int64_t)I.nx * I.ny));
         NodeVals<T, A> v;
         state_at<T>(s, I, x, y, z, v);
-        if (outA) outA[k] = (double)v.rho[0];
-        if (outB) outB[k] = (double)v.rho[1];
+        if (outA) outA[k] = I.shift[0] + (double)v.drho[0];
+        if (outB) outB[k] = I.shift[1] + (double)v.drho[1];
     }
 }
 
@@ -531,7 +605,7 @@ __global__ __launch_bounds__(256) void k_diag_planes(Inst I, const T* __restrict
         pull_node<T, A>(s, I, x, y, z, v);
         node_density<T, A>(I, v);
         if (in_sink(I.reset, x, y, z, I.nx, I.ny, I.nz)) acc[6] += sink_reset<T, A>(I, v);
-        const double ra = (double)v.rho[0], rb = (double)v.rho[1];
+        const double ra = I.shift[0] + (double)v.drho[0], rb = I.shift[1] + (double)v.drho[1];
         acc[0] += ra;
         acc[1] += rb;
         for (int c = 0; c < 2; ++c)
@@ -597,6 +671,14 @@ __global__ void k_fold_eacc(const Inst* __restrict__ insts, int n_inst, double* 
         eacc[k] = 0.0;
     }
     ebase[inst] += s;
+}
+
+// Plain streaming copy (16 bytes per lane, grid-stride): the HBM ceiling the
+// step kernel is compared with, and the calibration of the byte counters.
+__global__ __launch_bounds__(256) void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n16)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k < n16) dst[k] = src[k];
 }
 
 __global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v)

@@ -66,7 +66,8 @@ struct Inst {
     int32_t psi_exp;       // 0: psi = rho, 1: psi = 1 - exp(-rho)
     int32_t count_reset;   // 0: the next pull-time reset is not booked into E
     int64_t n;             // nodes
-    int64_t pstride;       // elements between consecutive (c, i) planes
+    int64_t ps;            // elements per (c, i) plane of one z-slab (nx*ny, padded)
+    int64_t slab;          // elements per z-slab: 2*19 planes
     int64_t base;          // element offset of this instance in the arena
     double tau[2];
     double g;
@@ -76,6 +77,13 @@ struct Inst {
     Sink cur;              // current sink (its nodes skip collision)
     int32_t item_begin, item_end;   // this instance's work items
 };
+
+// Arena element of population (c, i) at in-plane index xy = y*nx + x of
+// plane z: z-slab major, so the 38 planes of one z are contiguous.
+LBSC_HD int64_t eidx(const Inst& I, int c, int i, int z, int64_t xy)
+{
+    return (int64_t)z * I.slab + (int64_t)(c * kQ + i) * I.ps + xy;
+}
 
 // One block's work: an xy tile [x0, x0+tw) x [y0, y0+th) marched over z in
 // [z0, z0+nzc).

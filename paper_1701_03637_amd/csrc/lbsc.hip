@@ -43,8 +43,9 @@ struct lbsc_ctx {
     std::vector<lbsc_params> params;
     std::vector<Inst> inst;       // host copy of the device table
     std::vector<Item> items;
-    lbsc_tiles tiles{0, 0, 0, 0};
+    lbsc_tiles tiles{0, 0, 0, 0, 0};
     int nt = 256;
+    bool repull = false;          // k_step variant (see KEEP in kernels.h)
     size_t pop_elems = 0;         // elements per population buffer
     size_t max_items = 0;
     int max_nz = 0;
@@ -119,8 +120,9 @@ lbsc_status validate(const lbsc_params& p, int k, std::string& why)
     };
     if (p.nx < 1 || p.ny < 1 || p.nz < 1 || p.nx > 4096 || p.ny > 4096 || p.nz > 4096) return bad("size out of 1..4096");
     if ((int64_t)p.nx * p.ny * p.nz >= (int64_t(1) << 31)) return bad("nx*ny*nz must be < 2^31");
-    if ((int64_t)p.nx * p.ny * p.nz * (int64_t)elem_size(p.precision) >= (int64_t(1) << 32))
-        return bad("one population plane must be < 4 GiB");
+    if ((int64_t)(2 * lbsc::kQ) * ((int64_t)p.nx * p.ny + 64 + p.plane_pad) * (int64_t)elem_size(p.precision) >=
+        (int64_t(1) << 32))
+        return bad("one z-slab of 38 population planes must be < 4 GiB");
     if (!(p.tau[0] > 0.5) || !(p.tau[1] > 0.5)) return bad("tau must be > 0.5");
     if (!std::isfinite(p.g)) return bad("g not finite");
     if (p.psi != LBSC_PSI_RHO && p.psi != LBSC_PSI_EXP) return bad("unknown psi");
@@ -129,13 +131,17 @@ lbsc_status validate(const lbsc_params& p, int k, std::string& why)
     if (!std::isfinite(p.rho_h) || !std::isfinite(p.sink_radius)) return bad("sink parameters not finite");
     if (p.phi_delta[0] == p.phi_delta[1]) return bad("phi_delta[0] must differ from phi_delta[1]");
     if (!std::isfinite(p.shift[0]) || !std::isfinite(p.shift[1])) return bad("shift not finite");
+    if (p.plane_pad < 0 || p.plane_pad > (1 << 20)) return bad("plane_pad out of 0..2^20");
     return LBSC_OK;
 }
 
 // Work items of one instance for the schedule in `t` (see lbsc_tiles).
 void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int64_t total_nodes, std::vector<Item>& out)
 {
-    int tw = t.tw > 0 ? t.tw : (I.nx <= 128 ? I.nx : 64);
+    // Defaults from tile sweeps on MI355X: rows as wide as possible (up to
+    // 128), and about 512 blocks per context with at least 16 planes per
+    // z chunk (each chunk re-derives the densities of two extra planes).
+    int tw = t.tw > 0 ? t.tw : 128;
     tw = std::min({tw, I.nx, 128, nt});
     int th = t.th > 0 ? t.th : std::max(1, nt / tw);
     th = std::min({th, I.ny, 128, std::max(1, nt / tw)});
@@ -143,10 +149,9 @@ void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int64_
     const int cols = mx * my;
     int nzc = t.nzc;
     if (nzc <= 0) {
-        // About 2048 blocks for the whole context, at least 4 planes per chunk.
-        double want = 2048.0 * (double)I.n / (double)total_nodes / cols;
+        double want = 512.0 * (double)I.n / (double)total_nodes / cols;
         int chunks = std::max(1, (int)std::ceil(want));
-        chunks = std::min(chunks, std::max(1, I.nz / 4));
+        chunks = std::min(chunks, std::max(1, I.nz / 16));
         nzc = (I.nz + chunks - 1) / chunks;
     }
     nzc = std::min(nzc, I.nz);
@@ -169,6 +174,7 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
 {
     nt = t.nt > 0 ? t.nt : 256;
     if (nt != 256 && nt != 512) return fail(c, LBSC_E_ARG, "tiles.nt must be 256 or 512");
+    if (t.variant < 0 || t.variant > 2) return fail(c, LBSC_E_ARG, "tiles.variant must be 0, 1 or 2");
     if (t.tw > 128 || t.th > 128) return fail(c, LBSC_E_ARG, "tiles.tw and tiles.th must be <= 128");
     int64_t total = 0;
     for (auto& I : inst) total += I.n;
@@ -181,10 +187,9 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
     if (items.size() > c->max_items)
         return fail(c, LBSC_E_ARG, "schedule needs %zu work items, more than the %zu reserved", items.size(),
                     c->max_items);
-    constexpr int kFoot256 = lbsc::Foot<256>::kMax, kFoot512 = lbsc::Foot<512>::kMax;
+    const int foot = nt == 256 ? lbsc::Foot<256>::kMax : lbsc::Foot<512>::kMax;
     for (auto& it : items) {
-        if (it.tw * it.th > nt || it.tw > 128 || it.th > 128 ||
-            (it.tw + 2) * (it.th + 2) > (nt == 256 ? kFoot256 : kFoot512))
+        if (it.tw * it.th > nt || it.tw > 128 || it.th > 128 || (it.tw + 2) * (it.th + 2) > foot)
             return fail(c, LBSC_E_ARG, "internal: tile %dx%d does not fit %d threads", it.tw, it.th, nt);
         const Inst& I = inst[it.inst];
         if (it.x0 < 0 || it.y0 < 0 || it.z0 < 0 || it.x0 + it.tw > I.nx || it.y0 + it.th > I.ny ||
@@ -221,20 +226,26 @@ void drop_graphs(lbsc_ctx* c)
 
 int fill_grid(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 65536); }
 
-template <typename T, int NT>
+template <typename T, int NT, bool KEEP>
 hipError_t launch_step_t(lbsc_ctx* c, hipStream_t s, int src)
 {
     const int n = (int)c->items.size();
     const int grid = ((n + 7) / 8) * 8;
-    hipLaunchKernelGGL((lbsc::k_step<T, NT>), dim3(grid), dim3(NT), 0, s, c->d_inst(), c->d_items(), n,
+    hipLaunchKernelGGL((lbsc::k_step<T, NT, KEEP>), dim3(grid), dim3(NT), 0, s, c->d_inst(), c->d_items(), n,
                        (const T*)c->pop[src], (T*)c->pop[src ^ 1], c->d_eacc());
     return hipGetLastError();
+}
+
+template <typename T, bool KEEP>
+hipError_t launch_step_k(lbsc_ctx* c, hipStream_t s, int src)
+{
+    return c->nt == 512 ? launch_step_t<T, 512, KEEP>(c, s, src) : launch_step_t<T, 256, KEEP>(c, s, src);
 }
 
 template <typename T>
 hipError_t launch_step_p(lbsc_ctx* c, hipStream_t s, int src)
 {
-    return c->nt == 512 ? launch_step_t<T, 512>(c, s, src) : launch_step_t<T, 256>(c, s, src);
+    return c->repull ? launch_step_k<T, false>(c, s, src) : launch_step_k<T, true>(c, s, src);
 }
 
 hipError_t launch_step(lbsc_ctx* c, hipStream_t s, int src)
@@ -300,6 +311,7 @@ lbsc_status apply_schedule(lbsc_ctx* c, const lbsc_tiles& t)
     c->items.swap(items);
     c->inst.swap(inst);
     c->nt = nt;
+    c->repull = t.variant == 2;
     c->tiles = t;
     drop_graphs(c);
     if (c->bound) {
@@ -353,9 +365,10 @@ lbsc_status lbsc_create(int32_t n_inst, const lbsc_params* params, lbsc_ctx** ou
         I.psi_exp = p.psi == LBSC_PSI_EXP;
         I.count_reset = 0;
         I.n = (int64_t)p.nx * p.ny * p.nz;
-        I.pstride = (int64_t)align_up((size_t)I.n, 256);
+        I.ps = (int64_t)align_up((size_t)p.nx * p.ny, 64) + (int64_t)align_up((size_t)p.plane_pad, 64);
+        I.slab = 2 * lbsc::kQ * I.ps;
         I.base = (int64_t)off;
-        off += (size_t)(2 * lbsc::kQ) * (size_t)I.pstride;
+        off = align_up(off + (size_t)p.nz * (size_t)I.slab, 256);
         I.tau[0] = p.tau[0]; I.tau[1] = p.tau[1];
         I.g = p.g;
         I.shift[0] = c->precision == LBSC_FP64 ? 0.0 : p.shift[0];
@@ -378,7 +391,7 @@ lbsc_status lbsc_create(int32_t n_inst, const lbsc_params* params, lbsc_ctx** ou
     c->off_part = o; o = align_up(o + (size_t)c->max_nz * lbsc::kDiagVals * sizeof(double), kAlign);
     c->off_out = o; o = align_up(o + 64 * sizeof(double), kAlign);
     c->scratch_bytes = o;
-    lbsc_tiles t{0, 0, 0, 0};
+    lbsc_tiles t{0, 0, 0, 0, 0};
     if (apply_schedule(c, t)) {
         delete c;
         return LBSC_E_ARG;
@@ -582,11 +595,12 @@ lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
     if (s) return s;
     if (steps < 2) return fail(c, LBSC_E_ARG, "tune: steps must be >= 2");
     std::vector<lbsc_tiles> cands;
-    for (int nt : {256, 512}) {
-        if (nt == 512 && c->precision == LBSC_FP64) continue;  // 512 x FP64 exceeds the register file
-        for (int tw : {0, 16, 32, 64})
-            for (int nzc : {0, 4, 8, 16, 32, 64, 4096}) cands.push_back(lbsc_tiles{nt, tw, 0, nzc});
-    }
+    for (int variant : {1, 2})
+        for (int nt : {256, 512}) {
+            if (nt == 512 && c->precision == LBSC_FP64 && variant == 1) continue;  // exceeds the register file
+            for (int tw : {0, 32, 64, 128})
+                for (int nzc : {0, 8, 16, 32, 64}) cands.push_back(lbsc_tiles{nt, tw, 0, nzc, variant});
+        }
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -600,7 +614,7 @@ lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
         if (apply_schedule(c, t) != LBSC_OK) continue;
         // Skip schedules identical to one already timed.
         std::string key(reinterpret_cast<const char*>(c->items.data()), c->items.size() * sizeof(Item));
-        key += std::to_string(c->nt);
+        key += std::to_string(c->nt) + (c->repull ? "r" : "k");
         if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
         seen.push_back(key);
         if ((s = lbsc_step(c, 2))) break;  // warm-up
@@ -623,6 +637,7 @@ lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
     if (chosen) {
         *chosen = best_t;
         chosen->nt = c->nt;
+        chosen->variant = c->repull ? 2 : 1;
     }
     return LBSC_OK;
 }
@@ -758,7 +773,7 @@ lbsc_status lbsc_load(lbsc_ctx* c, const void* blob)
     memcpy(saved.data(), head.data() + sizeof h, saved.size() * sizeof(Inst));
     for (size_t k = 0; k < saved.size(); ++k) {
         const Inst &a = saved[k], &b2 = c->inst[k];
-        if (a.nx != b2.nx || a.ny != b2.ny || a.nz != b2.nz || a.base != b2.base || a.pstride != b2.pstride)
+        if (a.nx != b2.nx || a.ny != b2.ny || a.nz != b2.nz || a.base != b2.base || a.ps != b2.ps)
             return fail(c, LBSC_E_ARG, "load: instance %zu geometry differs", k);
     }
     HIPCHK(c, hipMemcpyAsync(c->pop[c->cur], b + head.size(), c->pop_elems * c->elem, hipMemcpyDeviceToDevice,
@@ -779,6 +794,18 @@ lbsc_status lbsc_load(lbsc_ctx* c, const void* blob)
     }
     c->step = h.step;
     return upload_table(c);
+}
+
+lbsc_status lbsc_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream)
+{
+    if (!dst || !src || bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16) return LBSC_E_ARG;
+    const int64_t n16 = (int64_t)(bytes / 16);
+    if (n16 == 0) return LBSC_OK;
+    if ((n16 + 255) / 256 > INT32_MAX) return LBSC_E_ARG;
+    const int grid = (int)((n16 + 255) / 256);
+    hipLaunchKernelGGL(lbsc::k_copy16, dim3(grid), dim3(256), 0, (hipStream_t)hip_stream, (const uint4*)src,
+                       (uint4*)dst, n16);
+    return hipGetLastError() == hipSuccess ? LBSC_OK : LBSC_E_HIP;
 }
 
 int32_t lbsc_selftest(void)
@@ -840,17 +867,18 @@ int32_t lbsc_selftest(void)
     const int dims[][3] = {{4, 4, 128}, {128, 128, 128}, {48, 48, 48}, {156, 156, 156}, {1, 1, 64}, {200, 7, 9}};
     for (auto& d : dims)
         for (int nt : {256, 512})
-            for (int tw : {0, 32, 64, 128})
+            for (int tw : {0, 8, 16, 32, 64, 128})
                 for (int nzc : {0, 4, 16}) {
                     Inst I{};
                     I.nx = d[0]; I.ny = d[1]; I.nz = d[2];
                     I.n = (int64_t)d[0] * d[1] * d[2];
                     std::vector<Item> items;
-                    instance_items(I, 0, lbsc_tiles{nt, tw, 0, nzc}, nt, I.n, items);
+                    instance_items(I, 0, lbsc_tiles{nt, tw, 0, nzc, 0}, nt, I.n, items);
                     std::vector<unsigned char> cover((size_t)I.n, 0);
                     for (auto& it : items) {
                         if (it.tw * it.th > nt || it.tw > 128 || it.th > 128) ++bad;
-                        if ((it.tw + 2) * (it.th + 2) > (nt == 256 ? Foot<256>::kMax : Foot<512>::kMax)) ++bad;
+                        const int foot = nt == 256 ? Foot<256>::kMax : Foot<512>::kMax;
+                        if ((it.tw + 2) * (it.th + 2) > foot) ++bad;
                         for (int z = it.z0; z < it.z0 + it.nzc; ++z)
                             for (int y = it.y0; y < it.y0 + it.th; ++y)
                                 for (int x = it.x0; x < it.x0 + it.tw; ++x) {

@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("shift", ctypes.c_double * 2),
         ("sink", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("plane_pad", ctypes.c_int32),
         ("rho_h", ctypes.c_double),
         ("sink_radius", ctypes.c_double),
         ("center", ctypes.c_double * 3),
@@ -63,7 +63,8 @@ class Diag(ctypes.Structure):
 
 
 class Tiles(ctypes.Structure):
-    _fields_ = [("nt", ctypes.c_int32), ("tw", ctypes.c_int32), ("th", ctypes.c_int32), ("nzc", ctypes.c_int32)]
+    _fields_ = [("nt", ctypes.c_int32), ("tw", ctypes.c_int32), ("th", ctypes.c_int32), ("nzc", ctypes.c_int32),
+                ("variant", ctypes.c_int32)]
 
 
 SYMBOLS = [
@@ -72,6 +73,7 @@ SYMBOLS = [
     "lbsc_init_from_populations", "lbsc_set_sink", "lbsc_step", "lbsc_set_graph", "lbsc_set_tiles",
     "lbsc_tune", "lbsc_num_items", "lbsc_read_density", "lbsc_read_observables", "lbsc_read_populations",
     "lbsc_diagnostics", "lbsc_checkpoint_bytes", "lbsc_save", "lbsc_load", "lbsc_selftest",
+    "lbsc_stream_copy",
 ]
 
 _lib = None
@@ -112,6 +114,7 @@ def load_library():
         "lbsc_save": (i32, [vp, vp]),
         "lbsc_load": (i32, [vp, vp]),
         "lbsc_selftest": (i32, []),
+        "lbsc_stream_copy": (i32, [vp, vp, ctypes.c_size_t, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -123,17 +126,29 @@ def load_library():
 
 def make_params(nx, ny, nz, *, wall_z=False, tau=(1.0, 1.0), g=0.9, psi="rho", precision="fp64",
                 shift=(0.04, 0.70), sink="none", rho_h=0.04, sink_radius=0.0, center=None,
-                phi_delta=(0.66, -0.66)) -> Params:
+                phi_delta=(0.66, -0.66), plane_pad=0) -> Params:
     if center is None:
         center = ((nx - 1) / 2, (ny - 1) / 2, (nz - 1) / 2)
     return Params(nx, ny, nz, int(bool(wall_z)), (ctypes.c_double * 2)(*tau), g,
                   PSI_EXP if psi == "exp" else PSI_RHO, PRECISIONS[precision], (ctypes.c_double * 2)(*shift),
-                  SINKS[sink], 0, rho_h, sink_radius, (ctypes.c_double * 3)(*center),
+                  SINKS[sink], plane_pad, rho_h, sink_radius, (ctypes.c_double * 3)(*center),
                   (ctypes.c_double * 2)(*phi_delta))
 
 
 def _ptr(t: torch.Tensor) -> int:
     return t.data_ptr()
+
+
+def stream_copy(dst: torch.Tensor, src: torch.Tensor):
+    """Copies src into dst (same byte size) with the library's streaming kernel
+    on torch's current stream."""
+    lib = load_library()
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    st = lib.lbsc_stream_copy(_ptr(dst), _ptr(src), nbytes,
+                              ctypes.c_void_p(torch.cuda.current_stream(src.device).cuda_stream))
+    if st != 0:
+        raise LbscError(st, "stream_copy")
 
 
 class Sim:
@@ -213,14 +228,14 @@ class Sim:
     def set_graph(self, steps: int):
         self._check(self._lib.lbsc_set_graph(self._h, int(steps)))
 
-    def set_tiles(self, nt=0, tw=0, th=0, nzc=0):
-        t = Tiles(nt, tw, th, nzc)
+    def set_tiles(self, nt=0, tw=0, th=0, nzc=0, variant=0):
+        t = Tiles(nt, tw, th, nzc, variant)
         self._check(self._lib.lbsc_set_tiles(self._h, ctypes.byref(t)))
 
     def tune(self, steps: int = 20):
         t = Tiles()
         self._check(self._lib.lbsc_tune(self._h, int(steps), ctypes.byref(t)))
-        return (t.nt, t.tw, t.th, t.nzc)
+        return (t.nt, t.tw, t.th, t.nzc, t.variant)
 
     def num_items(self) -> int:
         v = ctypes.c_int32()

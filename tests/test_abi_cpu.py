@@ -44,8 +44,7 @@ def test_create_validates_and_sizes(lib):
     assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == 0
     pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
     assert lib.lbsc_required_bytes(h, ctypes.byref(pb), ctypes.byref(sb)) == 0
-    n = 64 * 48 * 40
-    assert pb.value == 38 * ((n + 255) // 256 * 256) * 4
+    assert pb.value == 40 * 38 * ((64 * 48 + 63) // 64 * 64) * 4
     nit = ctypes.c_int32()
     assert lib.lbsc_num_items(h, ctypes.byref(nit)) == 0 and nit.value > 0
     # calls that need device buffers report an unbound context
@@ -73,9 +72,9 @@ def test_tile_schedule_errors(lib):
     h = ctypes.c_void_p()
     p = lbsc.make_params(32, 32, 32)
     assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == 0
-    for t in (lbsc.Tiles(128, 0, 0, 0), lbsc.Tiles(256, 200, 0, 0)):
+    for t in (lbsc.Tiles(128, 0, 0, 0, 0), lbsc.Tiles(32, 16, 2, 0, 0), lbsc.Tiles(256, 200, 0, 0, 0), lbsc.Tiles(256, 0, 0, 0, 3)):
         assert lib.lbsc_set_tiles(h, ctypes.byref(t)) == -1
-    assert lib.lbsc_set_tiles(h, ctypes.byref(lbsc.Tiles(512, 32, 16, 4))) == 0
+    assert lib.lbsc_set_tiles(h, ctypes.byref(lbsc.Tiles(512, 32, 16, 4, 2))) == 0
     nit = ctypes.c_int32()
     lib.lbsc_num_items(h, ctypes.byref(nit))
     assert nit.value == 1 * 2 * 8

@@ -1,0 +1,164 @@
+"""The GPU path reproduces the paper's physics with its own parameters
+(psi = 1 - exp(-rho), g = 3.6, tau = 1, FP64 storage).
+
+- Sec. III B: a 4x4x128 film equilibrated without the sink, then evaporating
+  towards rho_H in {0.035, 0.03, 0.02} for 10^6 steps: (x_H - d0 - x_I)^2 is
+  linear in t with slope 2K (sign-fixed Eq. (xt)).
+- Sec. III C: surface tension from static droplets (Laplace test), then a small
+  evaporating droplet against RK4 solutions of the sign-fixed Eqs.
+  (mass-dfsum-sim) and (drop-r-df4).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import lbinputs as li
+from oracle import analytic as an
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+CS2 = 1.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def lb():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_1701_03637_amd as lb
+    lb.load_library()
+    return lb
+
+
+@pytest.fixture(scope="module")
+def film_state(lb):
+    """Equilibrated paper film (sink off), as FP64 populations."""
+    p = lb.make_params(4, 4, 128, wall_z=True, g=3.6, psi="exp", precision="fp64")
+    sim = lb.Sim(p)
+    sim.set_graph(1000)
+    a, b = li.film(4, 4, 128, 64)
+    sim.init_from_density(a, b)
+    sim.step(200000)
+    f = sim.populations()
+    ra = sim.density(0)[:, 0, 0].cpu().numpy()
+    rb = sim.density(1)[:, 0, 0].cpu().numpy()
+    return f, ra, rb
+
+
+def test_film_coexistence_gpu(film_state):
+    f, ra, rb = film_state
+    rho_ma, rho_mi = ra[20:44].mean(), ra[84:108].mean()
+    assert abs(rho_mi - 0.036) < 0.001 and abs(rho_ma - 0.704) < 0.006, (rho_ma, rho_mi)
+
+
+@pytest.mark.parametrize("rho_h", [0.035, 0.03, 0.02])
+def test_film_sqrt_t_law_paper_length(lb, film_state, rho_h):
+    f, ra, rb = film_state
+    rho_ma, rho_mi, rho_t = ra[20:44].mean(), ra[84:108].mean(), ra[100] + rb[100]
+    p = lb.make_params(4, 4, 128, wall_z=True, g=3.6, psi="exp", precision="fp64")
+    sim = lb.Sim(p)
+    sim.set_graph(1000)
+    sim.init_from_populations(f)
+    x0 = sim.diagnostics()["z_interface"]
+    sim.set_sink("zmax", rho_h)
+    T, nrec = 1_000_000, 40
+    ts, xs = [], []
+    for k in range(nrec):
+        sim.step(T // nrec)
+        ts.append((k + 1) * (T // nrec))
+        xs.append(sim.diagnostics()["z_interface"])
+    ts, xs = np.array(ts, float), np.array(xs)
+    assert np.all(np.diff(xs) < 0), "film must evaporate"
+    x_h = 127.0
+    y = (x_h - xs) ** 2
+    sel = ts > 0.1 * T
+    p1, res, *_ = np.polyfit(ts[sel], y[sel], 1, full=True)
+    r2 = 1 - res[0] / np.sum((y[sel] - y[sel].mean()) ** 2)
+    ram = 0.5 * (rho_mi + rho_h)
+    D = an.diffusion_small_gradient(ram, rho_t - ram, 3.6, "exp")
+    K = an.film_rate_constant(D, rho_ma, rho_mi, rho_h)
+    ratio = p1[0] / (2 * K)
+    print(f"rho_H={rho_h}: x0={x0:.3f} x_I(1e6)={xs[-1]:.3f} slope/2K={ratio:.4f} R2={r2:.6f}")
+    assert r2 > 0.999
+    assert abs(ratio - 1) < 0.10
+
+
+@pytest.fixture(scope="module")
+def surface_tension(lb):
+    """gamma from static droplets: P_in - P_out = 2 gamma / R, with the
+    bulk pressure P = c_s^2 (rhoA + rhoB) + c_s^2 g psiA psiB."""
+    n = 64
+    inv_r, dp = [], []
+    for R0 in (8.0, 11.0, 14.0, 18.0):
+        sim = lb.Sim(lb.make_params(n, n, n, g=3.6, psi="exp", precision="fp32s", shift=(0.04, 0.70)))
+        sim.set_graph(100)
+        a, b = li.droplet(n, n, n, R0)
+        sim.init_from_density(a, b)
+        sim.step(6000)
+        ra, rb = sim.density(0).cpu().numpy(), sim.density(1).cpu().numpy()
+        P = CS2 * (ra + rb) + CS2 * 3.6 * (1 - np.exp(-ra)) * (1 - np.exp(-rb))
+        c = n // 2
+        p_in = P[c - 2:c + 2, c - 2:c + 2, c - 2:c + 2].mean()
+        p_out = np.concatenate([P[:4].ravel(), P[-4:].ravel()]).mean()
+        V = np.clip((ra - rb + 0.675) / 1.35, 0, 1).sum()
+        R = (3 * V / (4 * math.pi)) ** (1 / 3)
+        inv_r.append(1 / R)
+        dp.append(p_in - p_out)
+        sim.close()
+    slope, icpt = np.polyfit(inv_r, dp, 1)
+    return slope / 2, icpt, inv_r, dp
+
+
+def test_laplace_law(surface_tension):
+    gamma, icpt, inv_r, dp = surface_tension
+    print(f"gamma={gamma:.5f} intercept={icpt:.2e} dp={dp}")
+    assert gamma > 0
+    assert abs(icpt) < 0.05 * max(dp)
+
+
+def test_droplet_shrinks_like_the_radius_odes(lb, surface_tension):
+    gamma = surface_tension[0]
+    n, R0, RH, rho_h = 64, 16.0, 31.0, 0.02
+    p = lb.make_params(n, n, n, g=3.6, psi="exp", precision="fp64", sink="none", rho_h=rho_h, sink_radius=RH,
+                       phi_delta=(0.675, -0.675))
+    sim = lb.Sim(p)
+    sim.set_graph(100)
+    a, b = li.droplet(n, n, n, R0)
+    sim.init_from_density(a, b)
+    sim.step(4000)
+    ra = sim.density(0).cpu().numpy()
+    rb = sim.density(1).cpu().numpy()
+    c = n // 2
+    rho_ma0 = ra[c - 2:c + 2, c - 2:c + 2, c - 2:c + 2].mean()
+    zz, yy, xx = np.meshgrid(*(np.arange(n) - (n - 1) / 2,) * 3, indexing="ij")
+    r = np.sqrt(xx ** 2 + yy ** 2 + zz ** 2)
+    shell = (r > 27) & (r < 30)
+    rho_mi0 = ra[shell].mean()
+    rho_t = (ra + rb)[shell].mean()
+    sim.set_sink("sphere", rho_h, RH)
+    r_start = sim.diagnostics()["r_droplet"]
+    ts, rs = [0.0], [r_start]
+    for k in range(60):
+        sim.step(500)
+        d = sim.diagnostics()
+        ts.append(500.0 * (k + 1))
+        rs.append(d["r_droplet"])
+        if d["r_droplet"] < 8:
+            break
+    ts, rs = np.array(ts), np.array(rs)
+    ram = 0.5 * (rho_mi0 + rho_h)
+    D = an.diffusion_small_gradient(ram, rho_t - ram, 3.6, "exp")
+    d0 = 2.5
+    t_plain, r_plain = an.rk4(lambda R: an.droplet_rate_plain(R, RH, d0, D, rho_ma0, rho_mi0, rho_h),
+                              r_start, ts[-1], 50.0)
+    t_lap, r_lap = an.rk4(lambda R: an.droplet_rate_laplace(R, RH, d0, D, r_start, gamma, rho_ma0, rho_mi0, rho_h),
+                          r_start, ts[-1], 50.0)
+    plain = np.interp(ts, t_plain, r_plain)
+    lap = np.interp(ts, t_lap, r_lap)
+    big = rs > 10.0   # the paper uses diameters above 20 only
+    err_plain = np.max(np.abs(rs[big] - plain[big]))
+    err_lap = np.max(np.abs(rs[big] - lap[big]))
+    print(f"R: {np.round(rs[::4], 2)}\nplain: {np.round(plain[::4], 2)}\nlaplace: {np.round(lap[::4], 2)}")
+    print(f"max |R - law| plain={err_plain:.3f} laplace={err_lap:.3f} gamma={gamma:.4f} D={D:.4f}")
+    assert rs[-1] < r_start - 2, "droplet must evaporate"
+    assert err_lap < 1.0
