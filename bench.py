@@ -24,8 +24,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "2-comp D3Q19 MLUPS + % HBM peak; FP32/FP16/batched vs plain FP64 at stated error"
 HBM_PEAK_GBPS = 8000.0
-BYTES_PER_LU = {"fp64": 608, "fp32s": 304, "fp16s": 152}   # 2 comps x 19 x (read + write)
-DTYPE = {"fp64": "f64", "fp32s": "f32", "fp16s": "f32"}
+# 2 comps x 19 x (read + write) x element size; FP16N stores the rest
+# population in FP32 (2 x 2 x (18 x 2 + 4))
+BYTES_PER_LU = {"fp64": 608, "fp32s": 304, "fp16s": 152, "fp16n": 160}
+DTYPE = {"fp64": "f64", "fp32s": "f32", "fp16s": "f32", "fp16n": "f32"}
 
 
 def kernel_hash() -> str:
@@ -205,7 +207,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20000, help="timed steps of the headline workload")
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--diag-every", type=int, default=100)
-    ap.add_argument("--forms", default="fp64,fp16s,batched,large",
+    ap.add_argument("--forms", default="fp64,fp16s,fp16n,batched,large",
                     help="extra forms besides the fp32s headline (comma list, or 'none')")
     ap.add_argument("--graph", type=int, default=0, help="steps per HIP graph (0: direct launches)")
     ap.add_argument("--tune-steps", type=int, default=20, help="steps per candidate of the tile tuner (0: defaults)")
@@ -245,6 +247,14 @@ def main():
             extra["fp16s"] = f16
             del rho16
             print(f"# fp16s {f16['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        if "fp16n" in forms:
+            f16n, rho16n = form_single(lb, torch, w, "fp16n", args.steps, args.warmup, args.diag_every,
+                                       args.graph, args.tune_steps)
+            f16n["max_abs_drho_vs_fp64"] = float((rho16n - rho64).abs().max())
+            f16n["speedup_vs_fp64"] = f16n["mlups"] / f64["mlups"]
+            extra["fp16n"] = f16n
+            del rho16n
+            print(f"# fp16n {f16n['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         del rho64
     del rho32
     torch.cuda.empty_cache()

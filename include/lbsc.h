@@ -64,8 +64,12 @@ typedef enum lbsc_status {
 
 /* Storage precision of the populations. FP32S/FP16S store the deviation
  * f - w_i*shift[c] and compute in FP32; FP64 stores f and computes in FP64.
+ * FP16N stores a per-node shift: the rest deviation d_0 = f_0 - w_0 shift[c]
+ * in FP32 and the moving deviations as d_i - (w_i/w_0) d_0 of the same node
+ * in FP16 (zero at rest equilibrium; 160 bytes per lattice update), FP32
+ * arithmetic.
  * Global sums (mass, evaporated mass, interface) are FP64 in every form. */
-enum { LBSC_FP64 = 0, LBSC_FP32S = 1, LBSC_FP16S = 2 };
+enum { LBSC_FP64 = 0, LBSC_FP32S = 1, LBSC_FP16S = 2, LBSC_FP16N = 3 };
 enum { LBSC_PSI_RHO = 0, LBSC_PSI_EXP = 1 };
 /* Sink node sets: the plane z = nz-1; the six faces; all nodes at distance
  * >= sink_radius from center. */
@@ -78,7 +82,7 @@ typedef struct lbsc_params {
     double tau[2];           /* relaxation times tau^A, tau^B (> 0.5) */
     double g;                /* interaction strength g^{AB} = g^{BA} */
     int32_t psi;             /* LBSC_PSI_RHO or LBSC_PSI_EXP */
-    int32_t precision;       /* LBSC_FP64/FP32S/FP16S; equal for all instances */
+    int32_t precision;       /* LBSC_FP64/FP32S/FP16S/FP16N; equal for all instances */
     double shift[2];         /* rho0^c of shifted storage (ignored for FP64) */
     int32_t sink;            /* LBSC_SINK_* */
     int32_t plane_pad;       /* extra elements between population planes

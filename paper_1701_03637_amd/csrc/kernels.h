@@ -3,16 +3,23 @@
 // arXiv:1701.03637, Sec. II), written for gfx950 (wave64, no MFMA: the step
 // is a memory-bound stencil, not a contraction).
 //
-// Storage. The populations of one instance live in a z-slab-major SoA arena:
-//   arena[base + z*slab + (c*19 + i)*ps + y*nx + x],  slab = 38*ps,
-// so the 38 population planes of one z-plane are contiguous and a pull needs
-// only the three slab bases z-1, z, z+1 plus a 32-bit offset per lane.
+// Storage. The populations of one instance live in a z-slab-major arena: the
+// populations of one z-plane form a contiguous slab, so a pull needs only the
+// three slab bases z-1, z, z+1 plus one 32-bit in-plane offset per lane.
 // The stored buffer holds post-collision populations f*(t-1); the state S(t)
 // of the method (post-stream, post-sink) is obtained by pulling,
 //   f_i(x) = f*_i(x - e_i), or f*_opp(i)(x) across a z-seam wall,
 // followed by the sink reset of the sink that was active when S(t) formed.
-// Shifted storage keeps delta = f - w_i*rho0^c (rho0 = 0 for plain FP64);
-// arithmetic is FP64 for FP64 storage and FP32 otherwise.
+// Storage forms (policies St* below):
+//   FP64    38 planes of f, FP64 arithmetic;
+//   FP32S   38 planes of f - w_i rho0^c (constant shift), FP32 arithmetic;
+//   FP16S   the same deviations in FP16, FP32 arithmetic;
+//   FP16N   per-node shift: the rest deviation d_0 = f_0 - w_0 rho0 in FP32
+//           and the 18 moving deviations as h_i = d_i - k_i d_0 of the same
+//           node in FP16, k_i = w_i / w_0 (h = 0 at rest equilibrium), FP32
+//           arithmetic.
+// Register values are always deviations from the constant shift rho0^c
+// (rho0 = 0 for FP64).
 //
 // Fused step (one launch per time step): a block owns an xy tile and marches
 // along z with a three-plane ring of psi (tile plus a one-node halo) in LDS.
@@ -27,8 +34,38 @@
 
 namespace lbsc {
 
-template <typename T> struct Arith { using A = float; };
-template <> struct Arith<double> { using A = double; };
+// Storage policies: element type T of the population planes, arithmetic type
+// A, and whether the rest population carries a per-node shift (kNode).
+struct StF64 { using T = double; using A = double; static constexpr bool kNode = false; };
+struct StF32S { using T = float; using A = float; static constexpr bool kNode = false; };
+struct StF16S { using T = _Float16; using A = float; static constexpr bool kNode = false; };
+struct StF16N { using T = _Float16; using A = float; static constexpr bool kNode = true; };
+
+// Slab elements (of T) per in-plane element: 38 planes, or for FP16N
+// 36 FP16 planes plus two FP32 rest planes (= 4 FP16 planes).
+template <class S> constexpr int kSlabPlanes = S::kNode ? 40 : 2 * kQ;
+
+// FP16N encoding constants: k_i = w_i / w_0 as FP32 and 1/K with
+// K = 1 + sum_{i>0} k_i evaluated from those same FP32 values, so decoding
+// then summing a node reproduces the encoded density deviation.
+__host__ __device__ constexpr float kRatio(int i) { return (float)(wgt(i) / wgt(0)); }
+constexpr float kInvK = (float)(1.0 / (1.0 + 6.0 * (double)(float)(1.0 / 6.0) + 12.0 * (double)(float)(1.0 / 12.0)));
+
+// Byte offset of population plane (c, i) within a slab of plane stride ps.
+template <class S>
+__host__ __device__ __forceinline__ uint32_t plane_off(int c, int i, uint32_t ps)
+{
+    if constexpr (S::kNode)
+        return i == 0 ? (36u * ps * 2u + (uint32_t)c * ps * 4u) : ((uint32_t)(c * 18 + i - 1) * ps * 2u);
+    else
+        return (uint32_t)(c * kQ + i) * ps * (uint32_t)sizeof(typename S::T);
+}
+
+// Bytes per element of plane i.
+template <class S> __host__ __device__ constexpr uint32_t elem_bytes(int i)
+{
+    return (S::kNode && i == 0) ? 4u : (uint32_t)sizeof(typename S::T);
+}
 
 template <typename A> __device__ __forceinline__ A psi_of(A rho, int psi_exp);
 template <> __device__ __forceinline__ double psi_of<double>(double rho, int psi_exp)
@@ -44,7 +81,7 @@ template <> __device__ __forceinline__ float psi_of<float>(float rho, int psi_ex
 // Pull of one node: 2 x 19 populations (delta form) and the sink reset.
 // ---------------------------------------------------------------------------
 
-template <typename T, typename A>
+template <typename A>
 struct NodeVals {
     A f[2][kQ];
     A rho[2];    // rho0 + drho
@@ -91,21 +128,20 @@ __device__ __forceinline__ void bstore(_Float16 v, Rsrc r, uint32_t voff, uint32
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)voff, (int)soff, 0);
 }
 
-template <typename T, typename A>
-__device__ __forceinline__ void pull_node(const T* __restrict__ src, const Inst& I, int x, int y, int z,
-                                          NodeVals<T, A>& v)
+template <class S, typename A = typename S::A>
+__device__ __forceinline__ void pull_node(const typename S::T* __restrict__ src, const Inst& I, int x, int y, int z,
+                                          NodeVals<A>& v)
 {
+    using T = typename S::T;
     const int nx = I.nx, ny = I.ny, nz = I.nz;
-    constexpr uint32_t E = sizeof(T);
-    const uint32_t xs[3] = {(uint32_t)wrap(x - 1, nx) * E, (uint32_t)x * E, (uint32_t)wrap(x + 1, nx) * E};
-    const uint32_t ys[3] = {(uint32_t)(wrap(y - 1, ny) * nx) * E, (uint32_t)(y * nx) * E,
-                            (uint32_t)(wrap(y + 1, ny) * nx) * E};
+    const uint32_t xs[3] = {(uint32_t)wrap(x - 1, nx), (uint32_t)x, (uint32_t)wrap(x + 1, nx)};
+    const uint32_t ys[3] = {(uint32_t)(wrap(y - 1, ny) * nx), (uint32_t)(y * nx), (uint32_t)(wrap(y + 1, ny) * nx)};
     // z is block-uniform for every call, so the resources and the wall
     // branch are scalar.
     const bool wall_lo = I.wall_z && z == 0, wall_hi = I.wall_z && z == nz - 1;
     const Rsrc sl[3] = {slab_rsrc(src + (int64_t)wrap(z - 1, nz) * I.slab), slab_rsrc(src + (int64_t)z * I.slab),
                         slab_rsrc(src + (int64_t)wrap(z + 1, nz) * I.slab)};
-    const uint32_t psb = (uint32_t)I.ps * E;
+    const uint32_t ps = (uint32_t)I.ps;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
         // pull from x - e_i, or the reflected population across a wall
@@ -113,13 +149,56 @@ __device__ __forceinline__ void pull_node(const T* __restrict__ src, const Inst&
         const int q = refl ? opp(i) : i;
         const Rsrc r = refl ? sl[1] : sl[1 - ez(i)];
         const uint32_t xy = refl ? ys[1] + xs[1] : ys[1 - ey(i)] + xs[1 - ex(i)];
-        v.f[0][i] = (A)bload<T>(r, xy, (uint32_t)q * psb);
-        v.f[1][i] = (A)bload<T>(r, xy, (uint32_t)(kQ + q) * psb);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            if constexpr (S::kNode) {
+                // d_i = k_i d_0(source) + h_i(source)
+                const float d0 = bload<float>(r, xy * 4u, plane_off<S>(c, 0, ps));
+                if (i == 0) {
+                    v.f[c][0] = d0;
+                } else {
+                    const float h = (float)bload<T>(r, xy * 2u, plane_off<S>(c, q, ps));
+                    v.f[c][i] = kRatio(i) * d0 + h;
+                }
+            } else {
+                v.f[c][i] = (A)bload<T>(r, xy * (uint32_t)sizeof(T), plane_off<S>(c, q, ps));
+            }
+        }
     }
 }
 
-template <typename T, typename A>
-__device__ __forceinline__ void node_density(const Inst& I, NodeVals<T, A>& v)
+// Stores the node's f* (deviations in v) into slab z of dst.
+template <class S, typename A = typename S::A>
+__device__ __forceinline__ void store_node(typename S::T* __restrict__ dst, const Inst& I, int z, uint32_t xy,
+                                           const NodeVals<A>& v)
+{
+    using T = typename S::T;
+    const Rsrc dz = slab_rsrc(dst + (int64_t)z * I.slab);
+    const uint32_t ps = (uint32_t)I.ps;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        if constexpr (S::kNode) {
+            // moving deviations relative to k_i d_0 in FP16; the rest
+            // deviation takes their rounding so the decoded node sums to drho
+            // (up to FP32 rounding).
+            const float d0 = v.f[c][0];
+            float hsum = 0.f;
+#pragma unroll
+            for (int i = 1; i < kQ; ++i) {
+                const T h = (T)(v.f[c][i] - kRatio(i) * d0);
+                hsum += (float)h;
+                bstore(h, dz, xy * 2u, plane_off<S>(c, i, ps));
+            }
+            bstore((v.drho[c] - hsum) * kInvK, dz, xy * 4u, plane_off<S>(c, 0, ps));
+        } else {
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) bstore((T)v.f[c][i], dz, xy * (uint32_t)sizeof(T), plane_off<S>(c, i, ps));
+        }
+    }
+}
+
+template <typename A>
+__device__ __forceinline__ void node_density(const Inst& I, NodeVals<A>& v)
 {
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -148,8 +227,8 @@ __device__ __forceinline__ void absorb_rest(A (&f)[kQ], A total)
 
 // Sink reset (Sec. II C): A -> f^eq(rho_H, 0), B -> f^eq(rhoA + rhoB - rho_H, 0)
 // from the densities pulled in this step. Returns rhoA_pre - rho_H in FP64.
-template <typename T, typename A>
-__device__ __forceinline__ double sink_reset(const Inst& I, NodeVals<T, A>& v)
+template <typename A>
+__device__ __forceinline__ double sink_reset(const Inst& I, NodeVals<A>& v)
 {
     const double rho_h = I.reset.rho_h;
     const double flux = I.shift[0] + (double)v.drho[0] - rho_h;
@@ -169,7 +248,7 @@ __device__ __forceinline__ double sink_reset(const Inst& I, NodeVals<T, A>& v)
         absorb_rest(v.f[0], da);
         absorb_rest(v.f[1], db);
     }
-    node_density<T, A>(I, v);
+    node_density<A>(I, v);
     return flux;
 }
 
@@ -178,8 +257,8 @@ __device__ __forceinline__ double sink_reset(const Inst& I, NodeVals<T, A>& v)
 // S[c] = sum_{i>0} w_i psi^{cbar}(x + e_i) e_i, the neighbour sum of Eq. (sc).
 // ---------------------------------------------------------------------------
 
-template <typename T, typename A>
-__device__ __forceinline__ void collide_node(const Inst& I, NodeVals<T, A>& v, const A S[2][3], A psiA, A psiB)
+template <typename A>
+__device__ __forceinline__ void collide_node(const Inst& I, NodeVals<A>& v, const A S[2][3], A psiA, A psiB)
 {
     A j[2][3];
 #pragma unroll
@@ -268,12 +347,13 @@ __device__ __forceinline__ A block_sum_wave(A v)
 // plane-ahead density pass to its collision (two population sets live).
 // KEEP = false: the density pass keeps only the densities and the collision
 // pulls the node again (one set live, higher occupancy, second read from L2).
-template <typename T, int NT, bool KEEP>
+template <class St, int NT, bool KEEP>
 __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, const Item* __restrict__ items,
-                                             int n_items, const T* __restrict__ src, T* __restrict__ dst,
-                                             double* __restrict__ eacc)
+                                             int n_items, const typename St::T* __restrict__ src,
+                                             typename St::T* __restrict__ dst, double* __restrict__ eacc)
 {
-    using A = typename Arith<T>::A;
+    using T = typename St::T;
+    using A = typename St::A;
     constexpr int FP = Foot<NT>::kMax;
     __shared__ A psiS[3][2][FP];
     __shared__ double red[NT / 64];
@@ -298,31 +378,31 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
     const bool book = I.count_reset != 0 && I.reset.kind != kSinkNone;
     double eflux = 0.0;
 
-    NodeVals<T, A> cur, nxt;
+    NodeVals<A> cur, nxt;
 
     // Pull plane zq (logical z) into LDS slot sl; tile nodes keep their values.
     // Halo nodes first, so only one extra population set is live at a time.
-    auto load_plane = [&](int zq, int sl, NodeVals<T, A>& keep_or_tmp) {
+    auto load_plane = [&](int zq, int sl, NodeVals<A>& keep_or_tmp) {
         const int zp = psi_plane(zq, I.nz, I.wall_z);
         for (int r = t; r < nring; r += NT) {
             int fx, fy;
             ring_coord(r, tw, th, fx, fy);
             const int hx = wrap(it.x0 + fx, I.nx), hy = wrap(it.y0 + fy, I.ny);
-            NodeVals<T, A> h;
-            pull_node<T, A>(s, I, hx, hy, zp, h);
-            node_density<T, A>(I, h);
-            if (in_sink(I.reset, hx, hy, zp, I.nx, I.ny, I.nz)) sink_reset<T, A>(I, h);
+            NodeVals<A> h;
+            pull_node<St>(s, I, hx, hy, zp, h);
+            node_density<A>(I, h);
+            if (in_sink(I.reset, hx, hy, zp, I.nx, I.ny, I.nz)) sink_reset<A>(I, h);
             const int fi = (fy + 1) * row + fx + 1;
             psiS[sl][0][fi] = psi_of<A>(h.rho[0], I.psi_exp);
             psiS[sl][1][fi] = psi_of<A>(h.rho[1], I.psi_exp);
         }
         if (own) {
-            NodeVals<T, A> tmp;
-            NodeVals<T, A>& keep = KEEP ? keep_or_tmp : tmp;
-            pull_node<T, A>(s, I, x, y, zp, keep);
-            node_density<T, A>(I, keep);
+            NodeVals<A> tmp;
+            NodeVals<A>& keep = KEEP ? keep_or_tmp : tmp;
+            pull_node<St>(s, I, x, y, zp, keep);
+            node_density<A>(I, keep);
             if (in_sink(I.reset, x, y, zp, I.nx, I.ny, I.nz)) {
-                const double fl = sink_reset<T, A>(I, keep);
+                const double fl = sink_reset<A>(I, keep);
                 if (book && zq >= z0 && zq < z1) eflux += fl;
             }
             const int fi = (ty + 1) * row + tx + 1;
@@ -332,14 +412,14 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
     };
 
     // Collide plane z of the tile node held in v and store f* to dst.
-    auto collide_plane = [&](int z, NodeVals<T, A>& kept) {
+    auto collide_plane = [&](int z, NodeVals<A>& kept) {
         if (!own) return;
-        NodeVals<T, A> tmp;
-        NodeVals<T, A>& v = KEEP ? kept : tmp;
+        NodeVals<A> tmp;
+        NodeVals<A>& v = KEEP ? kept : tmp;
         if constexpr (!KEEP) {
-            pull_node<T, A>(s, I, x, y, z, v);
-            node_density<T, A>(I, v);
-            if (in_sink(I.reset, x, y, z, I.nx, I.ny, I.nz)) sink_reset<T, A>(I, v);
+            pull_node<St>(s, I, x, y, z, v);
+            node_density<A>(I, v);
+            if (in_sink(I.reset, x, y, z, I.nx, I.ny, I.nz)) sink_reset<A>(I, v);
         }
         const int sm = (z - z0) % 3, s0 = (z - z0 + 1) % 3, sp = (z - z0 + 2) % 3;
         const uint32_t xy = (uint32_t)y * (uint32_t)I.nx + (uint32_t)x;
@@ -369,16 +449,9 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
 #pragma unroll
                 for (int dd = 0; dd < 3; ++dd) S[c][dd] = (A)wgt(1) * S1[c][dd] + (A)wgt(7) * S2[c][dd];
             const int fc = (ty + 1) * row + tx + 1;
-            collide_node<T, A>(I, v, S, psiS[s0][0][fc], psiS[s0][1][fc]);
+            collide_node<A>(I, v, S, psiS[s0][0][fc], psiS[s0][1][fc]);
         }
-        const Rsrc dz = slab_rsrc(d + (int64_t)z * I.slab);
-        const uint32_t psb = (uint32_t)I.ps * (uint32_t)sizeof(T);
-        const uint32_t xyb = xy * (uint32_t)sizeof(T);
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) {
-            bstore((T)v.f[0][i], dz, xyb, (uint32_t)i * psb);
-            bstore((T)v.f[1][i], dz, xyb, (uint32_t)(kQ + i) * psb);
-        }
+        store_node<St>(d, I, z, xy, v);
     };
 
     load_plane(z0 - 1, 0, nxt);
@@ -414,17 +487,38 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
 // across a z-seam wall, by y itself as population opp(i).
 // ---------------------------------------------------------------------------
 
-template <typename T>
-__global__ void k_init_density(Inst I, const double* __restrict__ rhoA, const double* __restrict__ rhoB,
-                               T* __restrict__ dst)
+// Writes the stored value `val` (a full FP64 population) of plane (c, i) at
+// in-plane index xy of slab z; f0 is the slot node's own rest population,
+// which FP16N encodes the moving populations against.
+template <class S>
+__device__ __forceinline__ void put_slot(typename S::T* __restrict__ d, const Inst& I, int c, int i, int z,
+                                         int64_t xy, double val, double f0)
 {
-    using A = typename Arith<T>::A;
+    using T = typename S::T;
+    using A = typename S::A;
+    char* slab = reinterpret_cast<char*>(d + (int64_t)z * I.slab);
+    const uint32_t off = plane_off<S>(c, i, (uint32_t)I.ps) + (uint32_t)xy * elem_bytes<S>(i);
+    if constexpr (S::kNode) {
+        const float d0 = (float)(f0 - wgt(0) * I.shift[c]);
+        if (i == 0) *reinterpret_cast<float*>(slab + off) = d0;
+        else *reinterpret_cast<T*>(slab + off) = (T)((float)(val - wgt(i) * I.shift[c]) - kRatio(i) * d0);
+    } else {
+        *reinterpret_cast<T*>(slab + off) = (T)(A)(val - wgt(i) * I.shift[c]);
+    }
+}
+
+template <class S>
+__global__ void k_init_density(Inst I, const double* __restrict__ rhoA, const double* __restrict__ rhoB,
+                               typename S::T* __restrict__ dst)
+{
     const int64_t n = I.n;
+    const double* rho[2] = {rhoA, rhoB};
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(k % I.nx);
         const int y = (int)((k / I.nx) % I.ny);
         const int z = (int)(k / ((int64_t)I.nx * I.ny));
-        T* d = dst + I.base;
+        const int64_t xy = k - (int64_t)z * I.nx * I.ny;
+        typename S::T* d = dst + I.base;
 #pragma unroll
         for (int i = 0; i < kQ; ++i) {
             const int zt = z + ez(i);
@@ -433,26 +527,22 @@ __global__ void k_init_density(Inst I, const double* __restrict__ rhoA, const do
                 src = k;
             else
                 src = node_of(wrap(x + ex(i), I.nx), wrap(y + ey(i), I.ny), wrap(zt, I.nz), I.nx, I.ny);
-            const double fa = wgt(i) * rhoA[src];
-            const double fb = wgt(i) * rhoB[src];
-            const int64_t xy = k - (int64_t)z * I.nx * I.ny;
-            d[eidx(I, 0, i, z, xy)] = (T)(A)(fa - wgt(i) * I.shift[0]);
-            d[eidx(I, 1, i, z, xy)] = (T)(A)(fb - wgt(i) * I.shift[1]);
+            for (int c = 0; c < 2; ++c) put_slot<S>(d, I, c, i, z, xy, wgt(i) * rho[c][src], wgt(0) * rho[c][k]);
         }
     }
 }
 
 // From full FP64 populations f[(c*19 + i)*n + node].
-template <typename T>
-__global__ void k_init_pops(Inst I, const double* __restrict__ f, T* __restrict__ dst)
+template <class S>
+__global__ void k_init_pops(Inst I, const double* __restrict__ f, typename S::T* __restrict__ dst)
 {
-    using A = typename Arith<T>::A;
     const int64_t n = I.n;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(k % I.nx);
         const int y = (int)((k / I.nx) % I.ny);
         const int z = (int)(k / ((int64_t)I.nx * I.ny));
-        T* d = dst + I.base;
+        const int64_t xy = k - (int64_t)z * I.nx * I.ny;
+        typename S::T* d = dst + I.base;
 #pragma unroll
         for (int i = 0; i < kQ; ++i) {
             const int zt = z + ez(i);
@@ -465,9 +555,8 @@ __global__ void k_init_pops(Inst I, const double* __restrict__ f, T* __restrict_
                 src = node_of(wrap(x + ex(i), I.nx), wrap(y + ey(i), I.ny), wrap(zt, I.nz), I.nx, I.ny);
                 q = i;
             }
-            const int64_t xy = k - (int64_t)z * I.nx * I.ny;
             for (int c = 0; c < 2; ++c)
-                d[eidx(I, c, i, z, xy)] = (T)(A)(f[(int64_t)(c * kQ + q) * n + src] - wgt(i) * I.shift[c]);
+                put_slot<S>(d, I, c, i, z, xy, f[(int64_t)(c * kQ + q) * n + src], f[(int64_t)(c * kQ) * n + k]);
         }
     }
 }
@@ -476,40 +565,40 @@ __global__ void k_init_pops(Inst I, const double* __restrict__ f, T* __restrict_
 // Read-outs of S(t) in FP64.
 // ---------------------------------------------------------------------------
 
-template <typename T>
-__device__ __forceinline__ void state_at(const T* s, const Inst& I, int x, int y, int z,
-                                         NodeVals<T, typename Arith<T>::A>& v)
+template <class S>
+__device__ __forceinline__ void state_at(const typename S::T* s, const Inst& I, int x, int y, int z,
+                                         NodeVals<typename S::A>& v)
 {
-    using A = typename Arith<T>::A;
-    pull_node<T, A>(s, I, x, y, z, v);
-    node_density<T, A>(I, v);
-    if (in_sink(I.reset, x, y, z, I.nx, I.ny, I.nz)) sink_reset<T, A>(I, v);
+    using A = typename S::A;
+    pull_node<S>(s, I, x, y, z, v);
+    node_density<A>(I, v);
+    if (in_sink(I.reset, x, y, z, I.nx, I.ny, I.nz)) sink_reset<A>(I, v);
 }
 
-template <typename T>
-__global__ void k_read_density(Inst I, const T* __restrict__ src, double* __restrict__ outA,
+template <class S>
+__global__ void k_read_density(Inst I, const typename S::T* __restrict__ src, double* __restrict__ outA,
                                double* __restrict__ outB)
 {
-    using A = typename Arith<T>::A;
-    const T* s = src + I.base;
+    using A = typename S::A;
+    const typename S::T* s = src + I.base;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < I.n; k += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(k % I.nx), y = (int)((k / I.nx) % I.ny), z = (int)(k / ((int64_t)I.nx * I.ny));
-        NodeVals<T, A> v;
-        state_at<T>(s, I, x, y, z, v);
+        NodeVals<A> v;
+        state_at<S>(s, I, x, y, z, v);
         if (outA) outA[k] = I.shift[0] + (double)v.drho[0];
         if (outB) outB[k] = I.shift[1] + (double)v.drho[1];
     }
 }
 
-template <typename T>
-__global__ void k_read_pops(Inst I, const T* __restrict__ src, double* __restrict__ out)
+template <class S>
+__global__ void k_read_pops(Inst I, const typename S::T* __restrict__ src, double* __restrict__ out)
 {
-    using A = typename Arith<T>::A;
-    const T* s = src + I.base;
+    using A = typename S::A;
+    const typename S::T* s = src + I.base;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < I.n; k += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(k % I.nx), y = (int)((k / I.nx) % I.ny), z = (int)(k / ((int64_t)I.nx * I.ny));
-        NodeVals<T, A> v;
-        state_at<T>(s, I, x, y, z, v);
+        NodeVals<A> v;
+        state_at<S>(s, I, x, y, z, v);
         for (int c = 0; c < 2; ++c)
 #pragma unroll
             for (int i = 0; i < kQ; ++i)
@@ -519,16 +608,16 @@ __global__ void k_read_pops(Inst I, const T* __restrict__ src, double* __restric
 
 // Barycentric velocity U of Eq. (velw) from S(t) and its densities (already
 // written by k_read_density): U = (sum_c j^c + (F^A + F^B)/2) / sum_c rho^c.
-template <typename T>
-__global__ void k_read_velocity(Inst I, const T* __restrict__ src, const double* __restrict__ rhoA,
+template <class S>
+__global__ void k_read_velocity(Inst I, const typename S::T* __restrict__ src, const double* __restrict__ rhoA,
                                 const double* __restrict__ rhoB, double* __restrict__ U)
 {
-    using A = typename Arith<T>::A;
-    const T* s = src + I.base;
+    using A = typename S::A;
+    const typename S::T* s = src + I.base;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < I.n; k += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(k % I.nx), y = (int)((k / I.nx) % I.ny), z = (int)(k / ((int64_t)I.nx * I.ny));
-        NodeVals<T, A> v;
-        state_at<T>(s, I, x, y, z, v);
+        NodeVals<A> v;
+        state_at<S>(s, I, x, y, z, v);
         double num[3] = {0.0, 0.0, 0.0};
         for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -540,20 +629,20 @@ __global__ void k_read_velocity(Inst I, const T* __restrict__ src, const double*
         if (!in_sink(I.cur, x, y, z, I.nx, I.ny, I.nz)) {
             const double* rho[2] = {rhoA, rhoB};
             for (int c = 0; c < 2; ++c) {
-                double S[3] = {0.0, 0.0, 0.0};
+                double Sv[3] = {0.0, 0.0, 0.0};
 #pragma unroll
                 for (int i = 1; i < kQ; ++i) {
                     const int zn = psi_plane(z + ez(i), I.nz, I.wall_z);
                     const int64_t nb = node_of(wrap(x + ex(i), I.nx), wrap(y + ey(i), I.ny), zn, I.nx, I.ny);
                     const double r = rho[1 - c][nb];
                     const double p = I.psi_exp ? 1.0 - exp(-r) : r;
-                    S[0] += wgt(i) * p * ex(i);
-                    S[1] += wgt(i) * p * ey(i);
-                    S[2] += wgt(i) * p * ez(i);
+                    Sv[0] += wgt(i) * p * ex(i);
+                    Sv[1] += wgt(i) * p * ey(i);
+                    Sv[2] += wgt(i) * p * ez(i);
                 }
                 const double r = rho[c][k];
                 const double pc = I.psi_exp ? 1.0 - exp(-r) : r;
-                for (int dd = 0; dd < 3; ++dd) num[dd] += 0.5 * (-pc * I.g * S[dd]);
+                for (int dd = 0; dd < 3; ++dd) num[dd] += 0.5 * (-pc * I.g * Sv[dd]);
             }
         }
         const double rt = rhoA[k] + rhoB[k];
@@ -590,21 +679,22 @@ __device__ __forceinline__ void block_sum_n(A* vals, int nv, A* lds)
     __syncthreads();
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_diag_planes(Inst I, const T* __restrict__ src, double* __restrict__ part)
+template <class S>
+__global__ __launch_bounds__(256) void k_diag_planes(Inst I, const typename S::T* __restrict__ src,
+                                                     double* __restrict__ part)
 {
-    using A = typename Arith<T>::A;
+    using A = typename S::A;
     __shared__ double lds[kDiagVals * 4];
-    const T* s = src + I.base;
+    const typename S::T* s = src + I.base;
     const int z = blockIdx.x;
     const int area = I.nx * I.ny;
     double acc[kDiagVals] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = threadIdx.x; k < area; k += blockDim.x) {
         const int x = k % I.nx, y = k / I.nx;
-        NodeVals<T, A> v;
-        pull_node<T, A>(s, I, x, y, z, v);
-        node_density<T, A>(I, v);
-        if (in_sink(I.reset, x, y, z, I.nx, I.ny, I.nz)) acc[6] += sink_reset<T, A>(I, v);
+        NodeVals<A> v;
+        pull_node<S>(s, I, x, y, z, v);
+        node_density<A>(I, v);
+        if (in_sink(I.reset, x, y, z, I.nx, I.ny, I.nz)) acc[6] += sink_reset<A>(I, v);
         const double ra = I.shift[0] + (double)v.drho[0], rb = I.shift[1] + (double)v.drho[1];
         acc[0] += ra;
         acc[1] += rb;

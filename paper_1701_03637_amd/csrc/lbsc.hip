@@ -26,6 +26,9 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 size_t elem_size(int prec) { return prec == LBSC_FP64 ? 8 : (prec == LBSC_FP32S ? 4 : 2); }
 
+// Slab elements per in-plane element (see kSlabPlanes in kernels.h).
+int slab_planes(int prec) { return prec == LBSC_FP16N ? 40 : 2 * lbsc::kQ; }
+
 struct CkptHeader {
     uint64_t magic;
     int32_t n_inst, precision;
@@ -120,13 +123,13 @@ lbsc_status validate(const lbsc_params& p, int k, std::string& why)
     };
     if (p.nx < 1 || p.ny < 1 || p.nz < 1 || p.nx > 4096 || p.ny > 4096 || p.nz > 4096) return bad("size out of 1..4096");
     if ((int64_t)p.nx * p.ny * p.nz >= (int64_t(1) << 31)) return bad("nx*ny*nz must be < 2^31");
-    if ((int64_t)(2 * lbsc::kQ) * ((int64_t)p.nx * p.ny + 64 + p.plane_pad) * (int64_t)elem_size(p.precision) >=
-        (int64_t(1) << 32))
-        return bad("one z-slab of 38 population planes must be < 4 GiB");
+    if ((int64_t)slab_planes(p.precision) * ((int64_t)p.nx * p.ny + 64 + p.plane_pad) *
+            (int64_t)elem_size(p.precision) >= (int64_t(1) << 32))
+        return bad("one z-slab of population planes must be < 4 GiB");
     if (!(p.tau[0] > 0.5) || !(p.tau[1] > 0.5)) return bad("tau must be > 0.5");
     if (!std::isfinite(p.g)) return bad("g not finite");
     if (p.psi != LBSC_PSI_RHO && p.psi != LBSC_PSI_EXP) return bad("unknown psi");
-    if (p.precision < LBSC_FP64 || p.precision > LBSC_FP16S) return bad("unknown precision");
+    if (p.precision < LBSC_FP64 || p.precision > LBSC_FP16N) return bad("unknown precision");
     if (p.sink < LBSC_SINK_NONE || p.sink > LBSC_SINK_SPHERE) return bad("unknown sink kind");
     if (!std::isfinite(p.rho_h) || !std::isfinite(p.sink_radius)) return bad("sink parameters not finite");
     if (p.phi_delta[0] == p.phi_delta[1]) return bad("phi_delta[0] must differ from phi_delta[1]");
@@ -226,34 +229,36 @@ void drop_graphs(lbsc_ctx* c)
 
 int fill_grid(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 65536); }
 
-template <typename T, int NT, bool KEEP>
+template <class St, int NT, bool KEEP>
 hipError_t launch_step_t(lbsc_ctx* c, hipStream_t s, int src)
 {
+    using T = typename St::T;
     const int n = (int)c->items.size();
     const int grid = ((n + 7) / 8) * 8;
-    hipLaunchKernelGGL((lbsc::k_step<T, NT, KEEP>), dim3(grid), dim3(NT), 0, s, c->d_inst(), c->d_items(), n,
+    hipLaunchKernelGGL((lbsc::k_step<St, NT, KEEP>), dim3(grid), dim3(NT), 0, s, c->d_inst(), c->d_items(), n,
                        (const T*)c->pop[src], (T*)c->pop[src ^ 1], c->d_eacc());
     return hipGetLastError();
 }
 
-template <typename T, bool KEEP>
+template <class St, bool KEEP>
 hipError_t launch_step_k(lbsc_ctx* c, hipStream_t s, int src)
 {
-    return c->nt == 512 ? launch_step_t<T, 512, KEEP>(c, s, src) : launch_step_t<T, 256, KEEP>(c, s, src);
+    return c->nt == 512 ? launch_step_t<St, 512, KEEP>(c, s, src) : launch_step_t<St, 256, KEEP>(c, s, src);
 }
 
-template <typename T>
+template <class St>
 hipError_t launch_step_p(lbsc_ctx* c, hipStream_t s, int src)
 {
-    return c->repull ? launch_step_k<T, false>(c, s, src) : launch_step_k<T, true>(c, s, src);
+    return c->repull ? launch_step_k<St, false>(c, s, src) : launch_step_k<St, true>(c, s, src);
 }
 
 hipError_t launch_step(lbsc_ctx* c, hipStream_t s, int src)
 {
     switch (c->precision) {
-    case LBSC_FP64: return launch_step_p<double>(c, s, src);
-    case LBSC_FP32S: return launch_step_p<float>(c, s, src);
-    default: return launch_step_p<_Float16>(c, s, src);
+    case LBSC_FP64: return launch_step_p<lbsc::StF64>(c, s, src);
+    case LBSC_FP32S: return launch_step_p<lbsc::StF32S>(c, s, src);
+    case LBSC_FP16S: return launch_step_p<lbsc::StF16S>(c, s, src);
+    default: return launch_step_p<lbsc::StF16N>(c, s, src);
     }
 }
 
@@ -283,9 +288,10 @@ template <typename F>
 hipError_t by_precision(int prec, F&& f)
 {
     switch (prec) {
-    case LBSC_FP64: return f(double{});
-    case LBSC_FP32S: return f(float{});
-    default: return f(_Float16{});
+    case LBSC_FP64: return f(lbsc::StF64{});
+    case LBSC_FP32S: return f(lbsc::StF32S{});
+    case LBSC_FP16S: return f(lbsc::StF16S{});
+    default: return f(lbsc::StF16N{});
     }
 }
 
@@ -366,7 +372,7 @@ lbsc_status lbsc_create(int32_t n_inst, const lbsc_params* params, lbsc_ctx** ou
         I.count_reset = 0;
         I.n = (int64_t)p.nx * p.ny * p.nz;
         I.ps = (int64_t)align_up((size_t)p.nx * p.ny, 64) + (int64_t)align_up((size_t)p.plane_pad, 64);
-        I.slab = 2 * lbsc::kQ * I.ps;
+        I.slab = slab_planes(p.precision) * I.ps;
         I.base = (int64_t)off;
         off = align_up(off + (size_t)p.nz * (size_t)I.slab, 256);
         I.tau[0] = p.tau[0]; I.tau[1] = p.tau[1];
@@ -476,8 +482,9 @@ lbsc_status lbsc_init_from_density(lbsc_ctx* c, int32_t inst, const double* rhoA
     if (!rhoA || !rhoB) return fail(c, LBSC_E_ARG, "init: null density pointer");
     const Inst I = c->inst[inst];
     HIPCHK(c, by_precision(c->precision, [&](auto tag) {
-               using T = decltype(tag);
-               hipLaunchKernelGGL(lbsc::k_init_density<T>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I, rhoA,
+               using S = decltype(tag);
+               using T = typename S::T;
+               hipLaunchKernelGGL(lbsc::k_init_density<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I, rhoA,
                                   rhoB, (T*)c->pop[c->cur]);
                return hipGetLastError();
            }));
@@ -491,8 +498,9 @@ lbsc_status lbsc_init_from_populations(lbsc_ctx* c, int32_t inst, const double* 
     if (!f) return fail(c, LBSC_E_ARG, "init: null population pointer");
     const Inst I = c->inst[inst];
     HIPCHK(c, by_precision(c->precision, [&](auto tag) {
-               using T = decltype(tag);
-               hipLaunchKernelGGL(lbsc::k_init_pops<T>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I, f,
+               using S = decltype(tag);
+               using T = typename S::T;
+               hipLaunchKernelGGL(lbsc::k_init_pops<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I, f,
                                   (T*)c->pop[c->cur]);
                return hipGetLastError();
            }));
@@ -649,8 +657,9 @@ lbsc_status lbsc_read_density(lbsc_ctx* c, int32_t inst, int32_t comp, double* o
     if (!out || comp < 0 || comp > 1) return fail(c, LBSC_E_ARG, "read_density: bad component or pointer");
     const Inst I = c->inst[inst];
     HIPCHK(c, by_precision(c->precision, [&](auto tag) {
-               using T = decltype(tag);
-               hipLaunchKernelGGL(lbsc::k_read_density<T>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
+               using S = decltype(tag);
+               using T = typename S::T;
+               hipLaunchKernelGGL(lbsc::k_read_density<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
                                   (const T*)c->pop[c->cur], comp == 0 ? out : nullptr, comp == 1 ? out : nullptr);
                return hipGetLastError();
            }));
@@ -664,13 +673,14 @@ lbsc_status lbsc_read_observables(lbsc_ctx* c, int32_t inst, double* ra, double*
     if (u && (!ra || !rb)) return fail(c, LBSC_E_ARG, "read_observables: velocity needs both density arrays");
     const Inst I = c->inst[inst];
     HIPCHK(c, by_precision(c->precision, [&](auto tag) {
-               using T = decltype(tag);
+               using S = decltype(tag);
+               using T = typename S::T;
                if (ra || rb)
-                   hipLaunchKernelGGL(lbsc::k_read_density<T>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
+                   hipLaunchKernelGGL(lbsc::k_read_density<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
                                       (const T*)c->pop[c->cur], ra, rb);
                hipError_t e = hipGetLastError();
                if (e != hipSuccess || !u) return e;
-               hipLaunchKernelGGL(lbsc::k_read_velocity<T>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
+               hipLaunchKernelGGL(lbsc::k_read_velocity<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
                                   (const T*)c->pop[c->cur], (const double*)ra, (const double*)rb, u);
                return hipGetLastError();
            }));
@@ -684,8 +694,9 @@ lbsc_status lbsc_read_populations(lbsc_ctx* c, int32_t inst, double* f)
     if (!f) return fail(c, LBSC_E_ARG, "read_populations: null pointer");
     const Inst I = c->inst[inst];
     HIPCHK(c, by_precision(c->precision, [&](auto tag) {
-               using T = decltype(tag);
-               hipLaunchKernelGGL(lbsc::k_read_pops<T>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
+               using S = decltype(tag);
+               using T = typename S::T;
+               hipLaunchKernelGGL(lbsc::k_read_pops<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
                                   (const T*)c->pop[c->cur], f);
                return hipGetLastError();
            }));
@@ -699,8 +710,9 @@ lbsc_status lbsc_diagnostics(lbsc_ctx* c, int32_t inst, lbsc_diag* out)
     if (!out) return fail(c, LBSC_E_ARG, "diagnostics: null output");
     const Inst I = c->inst[inst];
     HIPCHK(c, by_precision(c->precision, [&](auto tag) {
-               using T = decltype(tag);
-               hipLaunchKernelGGL(lbsc::k_diag_planes<T>, dim3(I.nz), dim3(256), 0, c->stream, I,
+               using S = decltype(tag);
+               using T = typename S::T;
+               hipLaunchKernelGGL(lbsc::k_diag_planes<S>, dim3(I.nz), dim3(256), 0, c->stream, I,
                                   (const T*)c->pop[c->cur], c->d_part());
                return hipGetLastError();
            }));
@@ -856,6 +868,23 @@ int32_t lbsc_selftest(void)
         for (int h : hits)
             if (h != 1) ++bad;
     }
+    // Plane byte ranges of every storage form are disjoint and fill the slab.
+    auto check_layout = [&](auto tag) {
+        using S = decltype(tag);
+        for (uint32_t ps : {64u, 4160u, 262144u}) {
+            std::vector<std::pair<uint32_t, uint32_t>> r;
+            for (int c = 0; c < 2; ++c)
+                for (int i = 0; i < kQ; ++i) r.push_back({plane_off<S>(c, i, ps), plane_off<S>(c, i, ps) + ps * elem_bytes<S>(i)});
+            std::sort(r.begin(), r.end());
+            for (size_t k = 0; k + 1 < r.size(); ++k)
+                if (r[k].second != r[k + 1].first) ++bad;
+            if (r.front().first != 0 || r.back().second != (uint32_t)kSlabPlanes<S> * ps * (uint32_t)sizeof(typename S::T)) ++bad;
+        }
+    };
+    check_layout(StF64{});
+    check_layout(StF32S{});
+    check_layout(StF16S{});
+    check_layout(StF16N{});
     // psi planes stay in range.
     for (int nz : {1, 2, 5})
         for (int wall = 0; wall < 2; ++wall)

@@ -133,15 +133,16 @@ def test_fp64_droplet_ragged_tiles_and_sink_switch(lb):
 
 @pytest.mark.parametrize("tiles", [(256, 0, 0, 0, 1), (512, 0, 0, 0, 1), (256, 16, 4, 3, 1), (512, 32, 8, 7, 1),
                                    (256, 64, 2, 5, 1), (256, 0, 0, 0, 2), (512, 32, 8, 7, 2), (256, 64, 2, 5, 2)])
-def test_tile_schedules_bitwise_identical(lb, tiles):
+@pytest.mark.parametrize("precision", ["fp64", "fp16n"])
+def test_tile_schedules_bitwise_identical(lb, tiles, precision):
     """The result does not depend on the tile schedule (catches LDS halo races
     and ragged-tile indexing)."""
     nx, ny, nz = 70, 23, 19
     f0 = li.random_populations(nx, ny, nz, seed=3, base_a=0.3, base_b=0.4, amp=0.05)
-    ref = lb.Sim(lb.make_params(nx, ny, nz, psi="exp", g=2.0, sink="faces", rho_h=0.03))
+    ref = lb.Sim(lb.make_params(nx, ny, nz, psi="exp", g=2.0, sink="faces", rho_h=0.03, precision=precision))
     ref.init_from_populations(f0)
     ref.step(7)
-    sim = lb.Sim(lb.make_params(nx, ny, nz, psi="exp", g=2.0, sink="faces", rho_h=0.03))
+    sim = lb.Sim(lb.make_params(nx, ny, nz, psi="exp", g=2.0, sink="faces", rho_h=0.03, precision=precision))
     sim.set_tiles(*tiles)
     sim.init_from_populations(f0)
     sim.step(7)
@@ -192,7 +193,10 @@ def test_graph_replay_and_checkpoint_bitwise(lb):
     assert abs(dr["evaporated"] - dref["evaporated"]) < 1e-12
 
 
-@pytest.mark.parametrize("precision,tol_rho", [("fp32s", 1e-5), ("fp16s", 1e-3)])
+@pytest.mark.parametrize("precision,tol_rho", [("fp32s", 1e-5), ("fp16n", 2e-4),
+                                               pytest.param("fp16s", 1e-3, marks=pytest.mark.xfail(
+                                                   reason="constant-shift FP16 quantises the slow dense-phase "
+                                                          "dynamics of this sharp film; FP16N fixes it", strict=True))])
 def test_reduced_precision_film_against_oracle(lb, precision, tol_rho):
     w = li.film_small()
     sim, orc = _pair(lb, w.nx, w.ny, w.nz, precision=precision, psi=w.psi, g=w.g, sink=w.sink, wall_z=w.wall_z,
@@ -210,11 +214,12 @@ def test_reduced_precision_film_against_oracle(lb, precision, tol_rho):
     dg, do = sim.diagnostics(), orc.diagnostics()
     tot = do["mass"][0] + do["mass"][1]
     drift = abs(dg["mass"][0] + dg["mass"][1] - tot) / tot
-    assert drift < (1e-6 if precision == "fp32s" else 1e-3), drift
+    print(f"{precision}: total-mass drift {drift:.3e}")
+    assert drift < {"fp32s": 1e-6, "fp16n": 1e-6}.get(precision, 1e-3), drift
     assert abs(dg["z_interface"] - do["z_interface"]) < (0.01 if precision == "fp32s" else 0.1)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32s", 2e-6), ("fp16s", 2e-3)])
+@pytest.mark.parametrize("precision,tol", [("fp32s", 2e-6), ("fp16s", 2e-3), ("fp16n", 2e-5)])
 def test_reduced_precision_droplet_against_oracle(lb, precision, tol):
     nx = ny = nz = 40
     sim, orc = _pair(lb, nx, ny, nz, precision=precision, g=0.9, sink="faces", rho_h=0.04)
