@@ -232,6 +232,7 @@ def main():
                               args.tune_steps)
     print(f"# fp32s {head['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     extra = {}
+    rho64 = None
     if "fp64" in forms:
         f64, rho64 = form_single(lb, torch, w, "fp64", args.steps, args.warmup, args.diag_every, args.graph,
                                  args.tune_steps)
@@ -239,23 +240,18 @@ def main():
         head["speedup_vs_fp64"] = head["mlups"] / f64["mlups"]
         extra["fp64"] = f64
         print(f"# fp64 {f64['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
-        if "fp16s" in forms:
-            f16, rho16 = form_single(lb, torch, w, "fp16s", args.steps, args.warmup, args.diag_every,
-                                     args.graph, args.tune_steps)
-            f16["max_abs_drho_vs_fp64"] = float((rho16 - rho64).abs().max())
-            f16["speedup_vs_fp64"] = f16["mlups"] / f64["mlups"]
-            extra["fp16s"] = f16
-            del rho16
-            print(f"# fp16s {f16['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
-        if "fp16n" in forms:
-            f16n, rho16n = form_single(lb, torch, w, "fp16n", args.steps, args.warmup, args.diag_every,
-                                       args.graph, args.tune_steps)
-            f16n["max_abs_drho_vs_fp64"] = float((rho16n - rho64).abs().max())
-            f16n["speedup_vs_fp64"] = f16n["mlups"] / f64["mlups"]
-            extra["fp16n"] = f16n
-            del rho16n
-            print(f"# fp16n {f16n['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
-        del rho64
+    for prec in ("fp16s", "fp16n"):
+        if prec not in forms:
+            continue
+        r, rho = form_single(lb, torch, w, prec, args.steps, args.warmup, args.diag_every, args.graph,
+                             args.tune_steps)
+        if rho64 is not None:
+            r["max_abs_drho_vs_fp64"] = float((rho - rho64).abs().max())
+            r["speedup_vs_fp64"] = r["mlups"] / f64["mlups"]
+        extra[prec] = r
+        del rho
+        print(f"# {prec} {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    del rho64
     del rho32
     torch.cuda.empty_cache()
     if "batched" in forms:

@@ -47,9 +47,17 @@ template <class S> constexpr int kSlabPlanes = S::kNode ? 40 : 2 * kQ;
 
 // FP16N encoding constants: k_i = w_i / w_0 as FP32 and 1/K with
 // K = 1 + sum_{i>0} k_i evaluated from those same FP32 values, so decoding
-// then summing a node reproduces the encoded density deviation.
+// then summing a node reproduces the encoded density deviation. 1/K is split
+// into an FP32 head and tail: the head alone sits 4e-8 (relative) below 1/K,
+// and that fixed bias, applied to every stored rest population, drifts the
+// mass of each component (the two drifts cancel in the total).
 __host__ __device__ constexpr float kRatio(int i) { return (float)(wgt(i) / wgt(0)); }
-constexpr float kInvK = (float)(1.0 / (1.0 + 6.0 * (double)(float)(1.0 / 6.0) + 12.0 * (double)(float)(1.0 / 12.0)));
+constexpr double kK = 1.0 + 6.0 * (double)(float)(1.0 / 6.0) + 12.0 * (double)(float)(1.0 / 12.0);
+constexpr float kInvK = (float)(1.0 / kK);
+constexpr float kInvKLo = (float)(1.0 / kK - (double)kInvK);
+
+// y / K rounded once (to within a tail rounding): head product plus tail.
+__device__ __forceinline__ float div_k(float y) { return __builtin_fmaf(y, kInvK, y * kInvKLo); }
 
 // Byte offset of population plane (c, i) within a slab of plane stride ps.
 template <class S>
@@ -189,7 +197,7 @@ __device__ __forceinline__ void store_node(typename S::T* __restrict__ dst, cons
                 hsum += (float)h;
                 bstore(h, dz, xy * 2u, plane_off<S>(c, i, ps));
             }
-            bstore((v.drho[c] - hsum) * kInvK, dz, xy * 4u, plane_off<S>(c, 0, ps));
+            bstore(div_k(v.drho[c] - hsum), dz, xy * 4u, plane_off<S>(c, 0, ps));
         } else {
 #pragma unroll
             for (int i = 0; i < kQ; ++i) bstore((T)v.f[c][i], dz, xy * (uint32_t)sizeof(T), plane_off<S>(c, i, ps));

@@ -105,10 +105,16 @@ def surface_tension(lb):
         sim.step(60000)
         ra, rb = sim.density(0).cpu().numpy(), sim.density(1).cpu().numpy()
         P = CS2 * (ra + rb) + CS2 * 3.6 * (1 - np.exp(-ra)) * (1 - np.exp(-rb))
-        V = np.clip((ra - rb + 0.675) / 1.35, 0, 1).sum()
+        inside, outside = r < 5, r > 28
+        # Equimolar radius from the excess of component A over the measured
+        # outside bulk: a fixed-threshold phase field would count the
+        # Laplace-raised vapour minority of the whole box as droplet volume.
+        a_in, a_out = ra[inside].mean(), ra[outside].mean()
+        V = (ra - a_out).sum() / (a_in - a_out)
         R = (3 * V / (4 * math.pi)) ** (1 / 3)
-        p_in = P[r < 0.5 * R].mean()
-        p_out = P[r > R + 10].mean()
+        assert R + 6 < 28, R
+        p_in = P[inside].mean()
+        p_out = P[outside].mean()
         inv_r.append(1 / R)
         dp.append(p_in - p_out)
         sim.close()
