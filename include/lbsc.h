@@ -117,8 +117,13 @@ typedef struct lbsc_ctx lbsc_ctx;
  * xy tile tw x th (tw, th <= 128, tw*th <= nt), z chunk of nzc planes, and the
  * kernel variant: 1 keeps a node's pulled populations in registers from its
  * density pass to its collision, 2 pulls the node again for the collision
- * (fewer registers, more blocks per CU). Zero or negative fields mean "choose
- * automatically". */
+ * (fewer registers, more blocks per CU), 3 (FP32S / FP16S storage only) also
+ * keeps them but issues each plane's loads one plane ahead of use, with one
+ * barrier per plane; it needs one thread per halo node of a tile (the halo
+ * of a tile spanning the whole x or y extent is the tile itself), so tiles
+ * that break this are rejected. Variants give bitwise identical results.
+ * Zero or negative fields mean "choose automatically" (variant: 3 where it
+ * applies, else 1). */
 typedef struct lbsc_tiles {
     int32_t nt, tw, th, nzc, variant;
 } lbsc_tiles;
@@ -163,6 +168,9 @@ lbsc_status lbsc_step(lbsc_ctx* ctx, int64_t n);
 lbsc_status lbsc_set_graph(lbsc_ctx* ctx, int32_t steps);
 /* Sets the tile schedule (see lbsc_tiles). */
 lbsc_status lbsc_set_tiles(lbsc_ctx* ctx, const lbsc_tiles* tiles);
+/* The schedule in use: tw, th, nzc as requested (0 = automatic) and the
+ * resolved nt and kernel variant. */
+lbsc_status lbsc_get_tiles(const lbsc_ctx* ctx, lbsc_tiles* out);
 /* Times candidate tile schedules for `steps` steps each and keeps the
  * fastest; writes it to *chosen if non-NULL. The populations advance during
  * tuning, so call it before lbsc_init_*. */

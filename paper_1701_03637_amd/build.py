@@ -17,6 +17,9 @@ FLAGS = [
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
+    # multiply-adds fuse only within one source expression, so every kernel
+    # variant that runs the same device functions rounds identically
+    "-ffp-contract=on",
 ]
 
 

@@ -136,9 +136,22 @@ __device__ __forceinline__ void bstore(_Float16 v, Rsrc r, uint32_t voff, uint32
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)voff, (int)soff, 0);
 }
 
-template <class S, typename A = typename S::A>
-__device__ __forceinline__ void pull_node(const typename S::T* __restrict__ src, const Inst& I, int x, int y, int z,
-                                          NodeVals<A>& v)
+// Raw stored values of one pulled node, as loaded: the loads can be issued
+// well before the values are decoded. FP16N carries, per population, the
+// moving value h_i and the FP32 rest deviation d_0 of its source node.
+template <class S, bool NODE = S::kNode> struct RawNode {
+    typename S::T v[2][kQ];
+};
+template <class S> struct RawNode<S, true> {
+    float d0[2][kQ];
+    typename S::T h[2][kQ];
+};
+
+// Issues the loads of the pull of node (x, y, z): population i from
+// x - e_i, or the reflected population across a wall on the z seam.
+template <class S>
+__device__ __forceinline__ void pull_raw(const typename S::T* __restrict__ src, const Inst& I, int x, int y, int z,
+                                         RawNode<S>& w)
 {
     using T = typename S::T;
     const int nx = I.nx, ny = I.ny, nz = I.nz;
@@ -152,7 +165,6 @@ __device__ __forceinline__ void pull_node(const typename S::T* __restrict__ src,
     const uint32_t ps = (uint32_t)I.ps;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-        // pull from x - e_i, or the reflected population across a wall
         const bool refl = (ez(i) > 0 && wall_lo) || (ez(i) < 0 && wall_hi);
         const int q = refl ? opp(i) : i;
         const Rsrc r = refl ? sl[1] : sl[1 - ez(i)];
@@ -160,19 +172,39 @@ __device__ __forceinline__ void pull_node(const typename S::T* __restrict__ src,
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             if constexpr (S::kNode) {
-                // d_i = k_i d_0(source) + h_i(source)
-                const float d0 = bload<float>(r, xy * 4u, plane_off<S>(c, 0, ps));
-                if (i == 0) {
-                    v.f[c][0] = d0;
-                } else {
-                    const float h = (float)bload<T>(r, xy * 2u, plane_off<S>(c, q, ps));
-                    v.f[c][i] = kRatio(i) * d0 + h;
-                }
+                w.d0[c][i] = bload<float>(r, xy * 4u, plane_off<S>(c, 0, ps));
+                if (i != 0) w.h[c][i] = bload<T>(r, xy * 2u, plane_off<S>(c, q, ps));
             } else {
-                v.f[c][i] = (A)bload<T>(r, xy * (uint32_t)sizeof(T), plane_off<S>(c, q, ps));
+                w.v[c][i] = bload<T>(r, xy * (uint32_t)sizeof(T), plane_off<S>(c, q, ps));
             }
         }
     }
+}
+
+// Decodes the raw values into deviations f_i - w_i rho0.
+template <class S, typename A = typename S::A>
+__device__ __forceinline__ void decode_raw(const RawNode<S>& w, NodeVals<A>& v)
+{
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            if constexpr (S::kNode) {
+                // d_i = k_i d_0(source) + h_i(source)
+                v.f[c][i] = i == 0 ? w.d0[c][0] : kRatio(i) * w.d0[c][i] + (float)w.h[c][i];
+            } else {
+                v.f[c][i] = (A)w.v[c][i];
+            }
+        }
+}
+
+template <class S, typename A = typename S::A>
+__device__ __forceinline__ void pull_node(const typename S::T* __restrict__ src, const Inst& I, int x, int y, int z,
+                                          NodeVals<A>& v)
+{
+    RawNode<S> w;
+    pull_raw<S>(src, I, x, y, z, w);
+    decode_raw<S>(w, v);
 }
 
 // Stores the node's f* (deviations in v) into slab z of dst.
@@ -316,6 +348,38 @@ __device__ __forceinline__ void collide_node(const Inst& I, NodeVals<A>& v, cons
 // The fused step kernel.
 // ---------------------------------------------------------------------------
 
+// Neighbour sum of Eq. (sc) from the psi planes z-1, z, z+1 held in LDS
+// (each [2][footprint], row stride `row`): S[c] = sum_i w_i psi^{cbar}(x + e_i)
+// e_i, taken over opposite pairs as w_i e_i times the difference of psi across
+// the node, axis and diagonal classes accumulated separately and weighted
+// once. cI[1 + e] / rI[1 + e] are the footprint column / row of the
+// neighbour at offset e in x / y.
+template <typename A, int FP>
+__device__ __forceinline__ void force_sum(const A (*pm)[FP], const A (*p0)[FP], const A (*pp)[FP], const int cI[3],
+                                          const int rI[3], int row, A S[2][3])
+{
+    A S1[2][3] = {{0, 0, 0}, {0, 0, 0}}, S2[2][3] = {{0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int i = 1; i < kQ; i += 2) {
+        const A(*lp)[FP] = ez(i) < 0 ? pm : (ez(i) > 0 ? pp : p0);
+        const A(*lm)[FP] = ez(i) > 0 ? pm : (ez(i) < 0 ? pp : p0);
+        const int fp = rI[1 + ey(i)] * row + cI[1 + ex(i)];
+        const int fm = rI[1 - ey(i)] * row + cI[1 - ex(i)];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const A dpsi = lp[1 - c][fp] - lm[1 - c][fm];
+            A(&acc)[3] = i < 7 ? S1[c] : S2[c];
+            if (ex(i)) acc[0] += ex(i) > 0 ? dpsi : -dpsi;
+            if (ey(i)) acc[1] += ey(i) > 0 ? dpsi : -dpsi;
+            if (ez(i)) acc[2] += ez(i) > 0 ? dpsi : -dpsi;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd) S[c][dd] = (A)wgt(1) * S1[c][dd] + (A)wgt(7) * S2[c][dd];
+}
+
 template <int NT> struct Foot {
     // Largest (tw + 2)(th + 2) = tw*th + 2(tw + th) + 4 over tiles with
     // tw*th <= NT and tw, th <= min(NT, 128): tw + th peaks at the extremes.
@@ -432,30 +496,9 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
         const int sm = (z - z0) % 3, s0 = (z - z0 + 1) % 3, sp = (z - z0 + 2) % 3;
         const uint32_t xy = (uint32_t)y * (uint32_t)I.nx + (uint32_t)x;
         if (!in_sink(I.cur, x, y, z, I.nx, I.ny, I.nz)) {
-            // Neighbour sum of Eq. (sc) over opposite pairs: w_i e_i times the
-            // difference of psi across the node, axis and diagonal classes
-            // accumulated separately and weighted once.
-            A S1[2][3] = {{0, 0, 0}, {0, 0, 0}}, S2[2][3] = {{0, 0, 0}, {0, 0, 0}};
-#pragma unroll
-            for (int i = 1; i < kQ; i += 2) {
-                const int slp = ez(i) < 0 ? sm : (ez(i) > 0 ? sp : s0);
-                const int slm = ez(i) > 0 ? sm : (ez(i) < 0 ? sp : s0);
-                const int fp = (ty + 1 + ey(i)) * row + tx + 1 + ex(i);
-                const int fm = (ty + 1 - ey(i)) * row + tx + 1 - ex(i);
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const A dpsi = psiS[slp][1 - c][fp] - psiS[slm][1 - c][fm];
-                    A(&acc)[3] = i < 7 ? S1[c] : S2[c];
-                    if (ex(i)) acc[0] += ex(i) > 0 ? dpsi : -dpsi;
-                    if (ey(i)) acc[1] += ey(i) > 0 ? dpsi : -dpsi;
-                    if (ez(i)) acc[2] += ez(i) > 0 ? dpsi : -dpsi;
-                }
-            }
+            const int cI[3] = {tx, tx + 1, tx + 2}, rI[3] = {ty, ty + 1, ty + 2};
             A S[2][3];
-#pragma unroll
-            for (int c = 0; c < 2; ++c)
-#pragma unroll
-                for (int dd = 0; dd < 3; ++dd) S[c][dd] = (A)wgt(1) * S1[c][dd] + (A)wgt(7) * S2[c][dd];
+            force_sum<A, FP>(psiS[sm], psiS[s0], psiS[sp], cI, rI, row, S);
             const int fc = (ty + 1) * row + tx + 1;
             collide_node<A>(I, v, S, psiS[s0][0][fc], psiS[s0][1][fc]);
         }
@@ -474,6 +517,170 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
             __syncthreads();
             collide_plane(z + 1, nxt);
             __syncthreads();
+        }
+    }
+
+    if (book) {
+        double e = block_sum_wave(eflux);
+        if ((t & 63) == 0) red[t >> 6] = e;
+        __syncthreads();
+        if (t == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < NT / 64; ++w) sum += red[w];
+            eacc[k] += sum;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Software-pipelined step (FP32 arithmetic forms).
+//
+// Same tiles, arithmetic and results as k_step; the schedule differs:
+//  - the loads of plane z+2 (tile node and one halo node per thread) are
+//    issued before the barrier and collision of plane z and decoded after
+//    it, so their latency hides behind a plane of work;
+//  - four psi slots in LDS let a plane's psi be written while the previous
+//    plane's stencil is still being read: one barrier per plane;
+//  - where the tile spans the whole periodic x (or y) extent, the halo
+//    column (row) is the tile's own opposite column (row): the stencil
+//    index wraps inside the tile and nothing is pulled for it.
+// Every halo node must have its own thread (PipeTile::nring <= NT).
+// ---------------------------------------------------------------------------
+
+struct PipeTile {
+    int nrow;    // halo nodes in each of the two halo rows (0: y wraps in the tile)
+    int ncol;    // halo nodes in each of the two halo columns (0: x wraps in the tile)
+    int nring;   // 2 nrow + 2 ncol
+};
+
+__host__ __device__ inline PipeTile pipe_tile(int tw, int th, int nx, int ny)
+{
+    const bool xper = tw == nx, yper = th == ny;
+    PipeTile p;
+    p.nrow = yper ? 0 : (xper ? tw : tw + 2);
+    p.ncol = xper ? 0 : th;
+    p.nring = 2 * p.nrow + 2 * p.ncol;
+    return p;
+}
+
+template <class St, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_step_pipe(const Inst* __restrict__ insts, const Item* __restrict__ items,
+                                                  int n_items, const typename St::T* __restrict__ src,
+                                                  typename St::T* __restrict__ dst, double* __restrict__ eacc)
+{
+    using T = typename St::T;
+    using A = typename St::A;
+    constexpr int FP = Foot<NT>::kMax;
+    __shared__ A psiS[4][2][FP];
+    __shared__ double red[NT / 64];
+
+    const int k = xcd_item(blockIdx.x, n_items);
+    if (k >= n_items) return;
+    const Item it = items[k];
+    const Inst I = insts[it.inst];
+    const T* __restrict__ s = src + I.base;
+    T* __restrict__ d = dst + I.base;
+
+    const int t = threadIdx.x;
+    const int tw = it.tw, th = it.th;
+    const int row = tw + 2;
+    const bool xper = tw == I.nx, yper = th == I.ny;
+    const PipeTile pt = pipe_tile(tw, th, I.nx, I.ny);
+    const bool own = t < tw * th;
+    const int tx = own ? t % tw : 0;
+    const int ty = own ? t / tw : 0;
+    const int x = wrap(it.x0 + tx, I.nx);
+    const int y = wrap(it.y0 + ty, I.ny);
+    const int fo = (ty + 1) * row + tx + 1;
+    const int cI[3] = {xper && tx == 0 ? tw : tx, tx + 1, xper && tx == tw - 1 ? 1 : tx + 2};
+    const int rI[3] = {yper && ty == 0 ? th : ty, ty + 1, yper && ty == th - 1 ? 1 : ty + 2};
+
+    // This thread's halo node: two halo rows, then two halo columns.
+    const bool ring = t < pt.nring;
+    int fx = 0, fy = 0;
+    if (ring) {
+        if (t < 2 * pt.nrow) {
+            const bool lo = t < pt.nrow;
+            fy = lo ? -1 : th;
+            fx = (lo ? t : t - pt.nrow) - (xper ? 0 : 1);
+        } else {
+            const int r = t - 2 * pt.nrow;
+            const bool lo = r < pt.ncol;
+            fx = lo ? -1 : tw;
+            fy = lo ? r : r - pt.ncol;
+        }
+    }
+    const int hx = wrap(it.x0 + fx, I.nx), hy = wrap(it.y0 + fy, I.ny);
+    const int fh = (fy + 1) * row + fx + 1;
+
+    const int z0 = it.z0, z1 = it.z0 + it.nzc;
+    const bool book = I.count_reset != 0 && I.reset.kind != kSinkNone;
+    double eflux = 0.0;
+
+    RawNode<St> ro, rr;
+    NodeVals<A> va, vb;
+
+    auto issue = [&](int zq) {
+        const int zp = psi_plane(zq, I.nz, I.wall_z);
+        if (ring) pull_raw<St>(s, I, hx, hy, zp, rr);
+        if (own) pull_raw<St>(s, I, x, y, zp, ro);
+    };
+    // Densities (with the pull-time sink reset) of logical plane zq from the
+    // issued loads; psi to its LDS slot, the tile node's values to keep.
+    auto dens = [&](int zq, NodeVals<A>& keep) {
+        const int zp = psi_plane(zq, I.nz, I.wall_z);
+        A(*ps)[FP] = psiS[(zq - z0 + 1) & 3];
+        if (ring) {
+            NodeVals<A> h;
+            decode_raw<St>(rr, h);
+            node_density<A>(I, h);
+            if (in_sink(I.reset, hx, hy, zp, I.nx, I.ny, I.nz)) sink_reset<A>(I, h);
+            ps[0][fh] = psi_of<A>(h.rho[0], I.psi_exp);
+            ps[1][fh] = psi_of<A>(h.rho[1], I.psi_exp);
+        }
+        if (own) {
+            decode_raw<St>(ro, keep);
+            node_density<A>(I, keep);
+            if (in_sink(I.reset, x, y, zp, I.nx, I.ny, I.nz)) {
+                const double fl = sink_reset<A>(I, keep);
+                if (book && zq >= z0 && zq < z1) eflux += fl;
+            }
+            ps[0][fo] = psi_of<A>(keep.rho[0], I.psi_exp);
+            ps[1][fo] = psi_of<A>(keep.rho[1], I.psi_exp);
+        }
+    };
+    auto collide = [&](int z, NodeVals<A>& v) {
+        if (!own) return;
+        const uint32_t xy = (uint32_t)y * (uint32_t)I.nx + (uint32_t)x;
+        if (!in_sink(I.cur, x, y, z, I.nx, I.ny, I.nz)) {
+            A S[2][3];
+            force_sum<A, FP>(psiS[(z - z0) & 3], psiS[(z - z0 + 1) & 3], psiS[(z - z0 + 2) & 3], cI, rI, row, S);
+            collide_node<A>(I, v, S, psiS[(z - z0 + 1) & 3][0][fo], psiS[(z - z0 + 1) & 3][1][fo]);
+        }
+        store_node<St>(d, I, z, xy, v);
+    };
+
+    issue(z0 - 1);
+    dens(z0 - 1, va);
+    issue(z0);
+    dens(z0, va);
+    issue(z0 + 1);
+    dens(z0 + 1, vb);
+    if (z0 + 2 <= z1) issue(z0 + 2);
+    for (int z = z0; z < z1; z += 2) {
+        __syncthreads();
+        collide(z, va);
+        if (z + 2 <= z1) {
+            dens(z + 2, va);
+            if (z + 3 <= z1) issue(z + 3);
+        }
+        if (z + 1 < z1) {
+            __syncthreads();
+            collide(z + 1, vb);
+            if (z + 3 <= z1) {
+                dens(z + 3, vb);
+                if (z + 4 <= z1) issue(z + 4);
+            }
         }
     }
 

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "lbsc.h"
@@ -48,7 +49,7 @@ struct lbsc_ctx {
     std::vector<Item> items;
     lbsc_tiles tiles{0, 0, 0, 0, 0};
     int nt = 256;
-    bool repull = false;          // k_step variant (see KEEP in kernels.h)
+    int variant = 1;              // resolved k_step variant: 1 keep, 2 re-pull, 3 pipelined
     size_t pop_elems = 0;         // elements per population buffer
     size_t max_items = 0;
     int max_nz = 0;
@@ -173,11 +174,14 @@ void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int64_
             }
 }
 
-lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& items, std::vector<Inst>& inst, int& nt)
+lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& items, std::vector<Inst>& inst, int& nt,
+                        int& variant)
 {
     nt = t.nt > 0 ? t.nt : 256;
     if (nt != 256 && nt != 512) return fail(c, LBSC_E_ARG, "tiles.nt must be 256 or 512");
-    if (t.variant < 0 || t.variant > 2) return fail(c, LBSC_E_ARG, "tiles.variant must be 0, 1 or 2");
+    if (t.variant > 3) return fail(c, LBSC_E_ARG, "tiles.variant must be 0, 1, 2 or 3");
+    if (t.variant == 3 && (c->precision == LBSC_FP64 || c->precision == LBSC_FP16N))
+        return fail(c, LBSC_E_ARG, "tiles.variant 3 needs FP32S or FP16S storage");
     if (t.tw > 128 || t.th > 128) return fail(c, LBSC_E_ARG, "tiles.tw and tiles.th must be <= 128");
     int64_t total = 0;
     for (auto& I : inst) total += I.n;
@@ -191,6 +195,7 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
         return fail(c, LBSC_E_ARG, "schedule needs %zu work items, more than the %zu reserved", items.size(),
                     c->max_items);
     const int foot = nt == 256 ? lbsc::Foot<256>::kMax : lbsc::Foot<512>::kMax;
+    bool pipe_fits = c->precision == LBSC_FP32S || c->precision == LBSC_FP16S;
     for (auto& it : items) {
         if (it.tw * it.th > nt || it.tw > 128 || it.th > 128 || (it.tw + 2) * (it.th + 2) > foot)
             return fail(c, LBSC_E_ARG, "internal: tile %dx%d does not fit %d threads", it.tw, it.th, nt);
@@ -198,7 +203,11 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
         if (it.x0 < 0 || it.y0 < 0 || it.z0 < 0 || it.x0 + it.tw > I.nx || it.y0 + it.th > I.ny ||
             it.z0 + it.nzc > I.nz || it.tw < 1 || it.th < 1 || it.nzc < 1)
             return fail(c, LBSC_E_ARG, "internal: tile outside its lattice");
+        if (lbsc::pipe_tile(it.tw, it.th, I.nx, I.ny).nring > nt) pipe_fits = false;
     }
+    if (t.variant == 3 && !pipe_fits)
+        return fail(c, LBSC_E_ARG, "tiles.variant 3: a tile has more halo nodes than the %d threads", nt);
+    variant = t.variant > 0 ? t.variant : (pipe_fits ? 3 : 1);
     return LBSC_OK;
 }
 
@@ -246,10 +255,24 @@ hipError_t launch_step_k(lbsc_ctx* c, hipStream_t s, int src)
     return c->nt == 512 ? launch_step_t<St, 512, KEEP>(c, s, src) : launch_step_t<St, 256, KEEP>(c, s, src);
 }
 
+template <class St, int NT>
+hipError_t launch_pipe_t(lbsc_ctx* c, hipStream_t s, int src)
+{
+    using T = typename St::T;
+    const int n = (int)c->items.size();
+    const int grid = ((n + 7) / 8) * 8;
+    hipLaunchKernelGGL((lbsc::k_step_pipe<St, NT>), dim3(grid), dim3(NT), 0, s, c->d_inst(), c->d_items(), n,
+                       (const T*)c->pop[src], (T*)c->pop[src ^ 1], c->d_eacc());
+    return hipGetLastError();
+}
+
 template <class St>
 hipError_t launch_step_p(lbsc_ctx* c, hipStream_t s, int src)
 {
-    return c->repull ? launch_step_k<St, false>(c, s, src) : launch_step_k<St, true>(c, s, src);
+    if constexpr (!std::is_same_v<typename St::A, double> && !St::kNode)
+        if (c->variant == 3)
+            return c->nt == 512 ? launch_pipe_t<St, 512>(c, s, src) : launch_pipe_t<St, 256>(c, s, src);
+    return c->variant == 2 ? launch_step_k<St, false>(c, s, src) : launch_step_k<St, true>(c, s, src);
 }
 
 hipError_t launch_step(lbsc_ctx* c, hipStream_t s, int src)
@@ -307,8 +330,8 @@ lbsc_status apply_schedule(lbsc_ctx* c, const lbsc_tiles& t)
 {
     std::vector<Item> items;
     std::vector<Inst> inst = c->inst;
-    int nt = 256;
-    lbsc_status s = build_items(c, t, items, inst, nt);
+    int nt = 256, variant = 1;
+    lbsc_status s = build_items(c, t, items, inst, nt, variant);
     if (s) return s;
     if (c->bound) {
         s = fold_eacc(c);  // accumulators belong to the old item list
@@ -317,7 +340,7 @@ lbsc_status apply_schedule(lbsc_ctx* c, const lbsc_tiles& t)
     c->items.swap(items);
     c->inst.swap(inst);
     c->nt = nt;
-    c->repull = t.variant == 2;
+    c->variant = variant;
     c->tiles = t;
     drop_graphs(c);
     if (c->bound) {
@@ -590,6 +613,15 @@ lbsc_status lbsc_set_tiles(lbsc_ctx* c, const lbsc_tiles* t)
     return apply_schedule(c, *t);
 }
 
+lbsc_status lbsc_get_tiles(const lbsc_ctx* c, lbsc_tiles* out)
+{
+    if (!c || !out) return LBSC_E_ARG;
+    *out = c->tiles;
+    out->nt = c->nt;
+    out->variant = c->variant;
+    return LBSC_OK;
+}
+
 lbsc_status lbsc_num_items(const lbsc_ctx* c, int32_t* n)
 {
     if (!c || !n) return LBSC_E_ARG;
@@ -603,9 +635,10 @@ lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
     if (s) return s;
     if (steps < 2) return fail(c, LBSC_E_ARG, "tune: steps must be >= 2");
     std::vector<lbsc_tiles> cands;
-    for (int variant : {1, 2})
+    for (int variant : {1, 2, 3})
         for (int nt : {256, 512}) {
             if (nt == 512 && c->precision == LBSC_FP64 && variant == 1) continue;  // exceeds the register file
+            if (variant == 3 && c->precision != LBSC_FP32S && c->precision != LBSC_FP16S) continue;
             for (int tw : {0, 32, 64, 128})
                 for (int nzc : {0, 8, 16, 32, 64}) cands.push_back(lbsc_tiles{nt, tw, 0, nzc, variant});
         }
@@ -622,7 +655,7 @@ lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
         if (apply_schedule(c, t) != LBSC_OK) continue;
         // Skip schedules identical to one already timed.
         std::string key(reinterpret_cast<const char*>(c->items.data()), c->items.size() * sizeof(Item));
-        key += std::to_string(c->nt) + (c->repull ? "r" : "k");
+        key += std::to_string(c->nt) + "v" + std::to_string(c->variant);
         if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
         seen.push_back(key);
         if ((s = lbsc_step(c, 2))) break;  // warm-up
@@ -645,7 +678,7 @@ lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
     if (chosen) {
         *chosen = best_t;
         chosen->nt = c->nt;
-        chosen->variant = c->repull ? 2 : 1;
+        chosen->variant = c->variant;
     }
     return LBSC_OK;
 }

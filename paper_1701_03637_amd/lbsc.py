@@ -70,7 +70,7 @@ class Tiles(ctypes.Structure):
 SYMBOLS = [
     "lbsc_status_string", "lbsc_last_error", "lbsc_version", "lbsc_create", "lbsc_destroy",
     "lbsc_required_bytes", "lbsc_bind", "lbsc_set_stream", "lbsc_init_from_density",
-    "lbsc_init_from_populations", "lbsc_set_sink", "lbsc_step", "lbsc_set_graph", "lbsc_set_tiles",
+    "lbsc_init_from_populations", "lbsc_set_sink", "lbsc_step", "lbsc_set_graph", "lbsc_set_tiles", "lbsc_get_tiles",
     "lbsc_tune", "lbsc_num_items", "lbsc_read_density", "lbsc_read_observables", "lbsc_read_populations",
     "lbsc_diagnostics", "lbsc_checkpoint_bytes", "lbsc_save", "lbsc_load", "lbsc_selftest",
     "lbsc_stream_copy",
@@ -104,6 +104,7 @@ def load_library():
         "lbsc_step": (i32, [vp, i64]),
         "lbsc_set_graph": (i32, [vp, i32]),
         "lbsc_set_tiles": (i32, [vp, ctypes.POINTER(Tiles)]),
+        "lbsc_get_tiles": (i32, [vp, ctypes.POINTER(Tiles)]),
         "lbsc_tune": (i32, [vp, i32, ctypes.POINTER(Tiles)]),
         "lbsc_num_items": (i32, [vp, ctypes.POINTER(i32)]),
         "lbsc_read_density": (i32, [vp, i32, i32, vp]),
@@ -231,6 +232,12 @@ class Sim:
     def set_tiles(self, nt=0, tw=0, th=0, nzc=0, variant=0):
         t = Tiles(nt, tw, th, nzc, variant)
         self._check(self._lib.lbsc_set_tiles(self._h, ctypes.byref(t)))
+
+    def tiles(self):
+        """(nt, tw, th, nzc, variant) in use; nt and variant resolved."""
+        t = Tiles()
+        self._check(self._lib.lbsc_get_tiles(self._h, ctypes.byref(t)))
+        return (t.nt, t.tw, t.th, t.nzc, t.variant)
 
     def tune(self, steps: int = 20):
         t = Tiles()

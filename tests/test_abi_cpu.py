@@ -80,3 +80,32 @@ def test_tile_schedule_errors(lib):
     assert nit.value == 1 * 2 * 8
     assert lib.lbsc_set_graph(h, 3) == -1 and lib.lbsc_set_graph(h, 4) == 0
     lib.lbsc_destroy(h)
+
+
+def test_kernel_variant_resolution(lib):
+    """Variant 0 resolves to the pipelined step where every tile's halo has a
+    thread per node and the storage is FP32S / FP16S, else to the
+    register-keeping step; an explicit variant 3 that does not fit fails."""
+    from paper_1701_03637_amd import lbsc
+
+    def resolve(prec, n, tiles):
+        h = ctypes.c_void_p()
+        p = lbsc.make_params(*n, precision=prec)
+        assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == 0
+        rc = lib.lbsc_set_tiles(h, ctypes.byref(lbsc.Tiles(*tiles)))
+        out = lbsc.Tiles()
+        assert lib.lbsc_get_tiles(h, ctypes.byref(out)) == 0
+        lib.lbsc_destroy(h)
+        return rc, out.nt, out.variant
+
+    assert resolve("fp32s", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 256, 3)
+    assert resolve("fp16s", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 256, 3)
+    assert resolve("fp64", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 256, 1)
+    assert resolve("fp16n", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 256, 1)
+    # 128 x 2 tiles of a 256-wide lattice: 2 (128 + 2) + 2 x 2 = 264 halo nodes
+    assert resolve("fp32s", (256, 64, 32), (256, 128, 2, 0, 0)) == (0, 256, 1)
+    rc, _, _ = resolve("fp32s", (256, 64, 32), (256, 128, 2, 0, 3))
+    assert rc == -1
+    assert resolve("fp32s", (256, 64, 32), (512, 128, 4, 0, 3)) == (0, 512, 3)
+    assert resolve("fp16n", (64, 64, 64), (256, 64, 4, 0, 3))[0] == -1
+
