@@ -86,14 +86,15 @@ def timed_run(sim, steps, warmup, diag_every, torch):
     return wall_ms, step_ms, diag
 
 
-def form_single(lb, torch, w, precision, steps, warmup, diag_every, graph, tune_steps):
+def form_single(lb, torch, w, precision, steps, warmup, diag_every, graph, tune_steps, pin=None):
     sim = make_sim(lb, w, precision)
     a, b = w.densities()
-    tiles = None
-    if tune_steps:
+    if pin:
+        sim.set_tiles(*pin)
+    elif tune_steps:
         # the tuner advances the state, so initialise again afterwards
         sim.init_from_density(a, b)
-        tiles = sim.tune(tune_steps)
+        sim.tune(tune_steps)
     sim.init_from_density(a, b)
     d0 = sim.diagnostics()
     if graph:
@@ -113,7 +114,7 @@ def form_single(lb, torch, w, precision, steps, warmup, diag_every, graph, tune_
         "r_droplet": d1["r_droplet"],
         "evaporated": d1["evaporated"],
         "items_per_step": sim.num_items(),
-        "tiles": tiles,
+        "tiles": list(sim.tiles()),
     }
     out["hbm_frac_alg"] = out["alg_GBps"] / HBM_PEAK_GBPS
     rho = sim.density(0)
@@ -128,11 +129,10 @@ def form_batched(lb, torch, steps, warmup, diag_every, tune_steps):
               for w in ws]
     sim = lb.Sim(params)
     dens = [w.densities() for w in ws]
-    tiles = None
     if tune_steps:
         for k, (a, b) in enumerate(dens):
             sim.init_from_density(a, b, inst=k)
-        tiles = sim.tune(tune_steps)
+        sim.tune(tune_steps)
     for k, (a, b) in enumerate(dens):
         sim.init_from_density(a, b, inst=k)
     nodes = sum(w.nodes for w in ws)
@@ -161,7 +161,7 @@ def form_batched(lb, torch, steps, warmup, diag_every, tune_steps):
         "kernel_ms_per_step": step_ms / steps,
         "alg_GBps": nodes * 304 / (step_ms / steps * 1e-3) / 1e9,
         "items_per_step": sim.num_items(),
-        "tiles": tiles,
+        "tiles": list(sim.tiles()),
         "max_mass_drift_rel": drift,
     }
     res["hbm_frac_alg"] = res["alg_GBps"] / HBM_PEAK_GBPS
@@ -210,6 +210,8 @@ def main():
     ap.add_argument("--forms", default="fp64,fp16s,fp16n,batched,large",
                     help="extra forms besides the fp32s headline (comma list, or 'none')")
     ap.add_argument("--graph", type=int, default=0, help="steps per HIP graph (0: direct launches)")
+    ap.add_argument("--tiles", default="",
+                    help="pin the headline schedule as nt,tw,th,nzc,variant (skips its tuner)")
     ap.add_argument("--tune-steps", type=int, default=20, help="steps per candidate of the tile tuner (0: defaults)")
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -228,8 +230,11 @@ def main():
     forms = [f for f in args.forms.split(",") if f and f != "none"]
 
     w = li.droplet_128()
+    pin = tuple(int(v) for v in args.tiles.split(",")) if args.tiles else None
+    if pin is not None and len(pin) != 5:
+        sys.exit("--tiles needs five integers: nt,tw,th,nzc,variant")
     head, rho32 = form_single(lb, torch, w, "fp32s", args.steps, args.warmup, args.diag_every, args.graph,
-                              args.tune_steps)
+                              args.tune_steps, pin)
     print(f"# fp32s {head['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     extra = {}
     rho64 = None

@@ -122,18 +122,23 @@ template <> __device__ __forceinline__ _Float16 bload<_Float16>(Rsrc r, uint32_t
     return __builtin_bit_cast(_Float16, (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0));
 }
 
+// Population stores carry the non-temporal cache policy (bit 1 of the
+// auxiliary operand): the next step reads them only after the whole lattice
+// has been written, so there is no reuse to keep them in cache for.
+constexpr int kStorePolicy = 2;
+
 __device__ __forceinline__ void bstore(float v, Rsrc r, uint32_t voff, uint32_t soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)voff, (int)soff, kStorePolicy);
 }
 __device__ __forceinline__ void bstore(double v, Rsrc r, uint32_t voff, uint32_t soff)
 {
     using U2 = unsigned int __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, (int)voff, (int)soff, kStorePolicy);
 }
 __device__ __forceinline__ void bstore(_Float16 v, Rsrc r, uint32_t voff, uint32_t soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)voff, (int)soff, kStorePolicy);
 }
 
 // Raw stored values of one pulled node, as loaded: the loads can be issued
@@ -407,6 +412,15 @@ __device__ __forceinline__ int xcd_item(int b, int n_items)
     return (b & 7) * per + (b >> 3);
 }
 
+// Lane 0's value as a wave-uniform (scalar-register) double.
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 template <typename A>
 __device__ __forceinline__ A block_sum_wave(A v)
 {
@@ -563,6 +577,31 @@ __host__ __device__ inline PipeTile pipe_tile(int tw, int th, int nx, int ny)
     return p;
 }
 
+// Halo node r < nring in tile coordinates (fx, fy): the two halo rows, then
+// the two halo columns.
+__host__ __device__ inline void pipe_ring_node(int r, const PipeTile& p, int tw, int th, bool xper, int& fx, int& fy)
+{
+    if (r < 2 * p.nrow) {
+        const bool lo = r < p.nrow;
+        fy = lo ? -1 : th;
+        fx = (lo ? r : r - p.nrow) - (xper ? 0 : 1);
+    } else {
+        const int q = r - 2 * p.nrow;
+        const bool lo = q < p.ncol;
+        fx = lo ? -1 : tw;
+        fy = lo ? q : q - p.ncol;
+    }
+}
+
+// Footprint column (row) of the neighbours at offsets -1, 0, +1 of tile
+// column (row) a of extent w; `per`: the tile spans the periodic extent.
+__host__ __device__ inline void pipe_stencil(int a, int w, bool per, int out[3])
+{
+    out[0] = per && a == 0 ? w : a;
+    out[1] = a + 1;
+    out[2] = per && a == w - 1 ? 1 : a + 2;
+}
+
 template <class St, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_step_pipe(const Inst* __restrict__ insts, const Item* __restrict__ items,
                                                   int n_items, const typename St::T* __restrict__ src,
@@ -592,67 +631,67 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const int x = wrap(it.x0 + tx, I.nx);
     const int y = wrap(it.y0 + ty, I.ny);
     const int fo = (ty + 1) * row + tx + 1;
-    const int cI[3] = {xper && tx == 0 ? tw : tx, tx + 1, xper && tx == tw - 1 ? 1 : tx + 2};
-    const int rI[3] = {yper && ty == 0 ? th : ty, ty + 1, yper && ty == th - 1 ? 1 : ty + 2};
+    int cI[3], rI[3];
+    pipe_stencil(tx, tw, xper, cI);
+    pipe_stencil(ty, th, yper, rI);
 
-    // This thread's halo node: two halo rows, then two halo columns.
+    // This thread's halo node.
     const bool ring = t < pt.nring;
     int fx = 0, fy = 0;
-    if (ring) {
-        if (t < 2 * pt.nrow) {
-            const bool lo = t < pt.nrow;
-            fy = lo ? -1 : th;
-            fx = (lo ? t : t - pt.nrow) - (xper ? 0 : 1);
-        } else {
-            const int r = t - 2 * pt.nrow;
-            const bool lo = r < pt.ncol;
-            fx = lo ? -1 : tw;
-            fy = lo ? r : r - pt.ncol;
-        }
-    }
+    if (ring) pipe_ring_node(t, pt, tw, th, xper, fx, fy);
     const int hx = wrap(it.x0 + fx, I.nx), hy = wrap(it.y0 + fy, I.ny);
     const int fh = (fy + 1) * row + fx + 1;
+    // Sink membership along the march: one packed z interval per column.
+    const uint32_t zr_own = sink_zrange(I.reset, x, y, I.nx, I.ny, I.nz);
+    const uint32_t zr_cur = sink_zrange(I.cur, x, y, I.nx, I.ny, I.nz);
+    const uint32_t zr_ring = sink_zrange(I.reset, hx, hy, I.nx, I.ny, I.nz);
 
     const int z0 = it.z0, z1 = it.z0 + it.nzc;
     const bool book = I.count_reset != 0 && I.reset.kind != kSinkNone;
-    double eflux = 0.0;
+    // Evaporated mass of this wave: each plane's sink fluxes are summed over
+    // the wave (fixed tree order) into one wave-uniform double, so no
+    // per-lane accumulator occupies registers across the march.
+    double ewave = 0.0;
 
     RawNode<St> ro, rr;
     NodeVals<A> va, vb;
 
-    auto issue = [&](int zq) {
+    auto issue_into = [&](int zq, RawNode<St>& wo, RawNode<St>& wr) {
         const int zp = psi_plane(zq, I.nz, I.wall_z);
-        if (ring) pull_raw<St>(s, I, hx, hy, zp, rr);
-        if (own) pull_raw<St>(s, I, x, y, zp, ro);
+        if (ring) pull_raw<St>(s, I, hx, hy, zp, wr);
+        if (own) pull_raw<St>(s, I, x, y, zp, wo);
     };
+    auto issue = [&](int zq) { issue_into(zq, ro, rr); };
     // Densities (with the pull-time sink reset) of logical plane zq from the
     // issued loads; psi to its LDS slot, the tile node's values to keep.
-    auto dens = [&](int zq, NodeVals<A>& keep) {
+    auto dens_from = [&](int zq, NodeVals<A>& keep, const RawNode<St>& wo, const RawNode<St>& wr) {
         const int zp = psi_plane(zq, I.nz, I.wall_z);
+        double fl = 0.0;
         A(*ps)[FP] = psiS[(zq - z0 + 1) & 3];
         if (ring) {
             NodeVals<A> h;
-            decode_raw<St>(rr, h);
+            decode_raw<St>(wr, h);
             node_density<A>(I, h);
-            if (in_sink(I.reset, hx, hy, zp, I.nx, I.ny, I.nz)) sink_reset<A>(I, h);
+            if (in_zrange_sink(zr_ring, zp)) sink_reset<A>(I, h);
             ps[0][fh] = psi_of<A>(h.rho[0], I.psi_exp);
             ps[1][fh] = psi_of<A>(h.rho[1], I.psi_exp);
         }
         if (own) {
-            decode_raw<St>(ro, keep);
+            decode_raw<St>(wo, keep);
             node_density<A>(I, keep);
-            if (in_sink(I.reset, x, y, zp, I.nx, I.ny, I.nz)) {
-                const double fl = sink_reset<A>(I, keep);
-                if (book && zq >= z0 && zq < z1) eflux += fl;
-            }
+            if (in_zrange_sink(zr_own, zp)) fl = sink_reset<A>(I, keep);
             ps[0][fo] = psi_of<A>(keep.rho[0], I.psi_exp);
             ps[1][fo] = psi_of<A>(keep.rho[1], I.psi_exp);
         }
+        if (book && zq >= z0 && zq < z1 && __builtin_amdgcn_ballot_w64(fl != 0.0)) {
+            ewave = wave_uniform(ewave + block_sum_wave(fl));
+        }
     };
+    auto dens = [&](int zq, NodeVals<A>& keep) { dens_from(zq, keep, ro, rr); };
     auto collide = [&](int z, NodeVals<A>& v) {
         if (!own) return;
         const uint32_t xy = (uint32_t)y * (uint32_t)I.nx + (uint32_t)x;
-        if (!in_sink(I.cur, x, y, z, I.nx, I.ny, I.nz)) {
+        if (!in_zrange_sink(zr_cur, z)) {
             A S[2][3];
             force_sum<A, FP>(psiS[(z - z0) & 3], psiS[(z - z0 + 1) & 3], psiS[(z - z0 + 2) & 3], cI, rI, row, S);
             collide_node<A>(I, v, S, psiS[(z - z0 + 1) & 3][0][fo], psiS[(z - z0 + 1) & 3][1][fo]);
@@ -660,13 +699,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         store_node<St>(d, I, z, xy, v);
     };
 
-    issue(z0 - 1);
-    dens(z0 - 1, va);
-    issue(z0);
-    dens(z0, va);
-    issue(z0 + 1);
-    dens(z0 + 1, vb);
-    if (z0 + 2 <= z1) issue(z0 + 2);
+    // Prologue: two planes in flight at a time (the second pair of raw sets
+    // is dead before the loop's working set is live).
+    {
+        RawNode<St> ro2, rr2;
+        issue_into(z0 - 1, ro2, rr2);
+        issue(z0);
+        dens_from(z0 - 1, va, ro2, rr2);
+        issue_into(z0 + 1, ro2, rr2);
+        dens(z0, va);
+        if (z0 + 2 <= z1) issue(z0 + 2);
+        dens_from(z0 + 1, vb, ro2, rr2);
+    }
     for (int z = z0; z < z1; z += 2) {
         __syncthreads();
         collide(z, va);
@@ -685,7 +729,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
 
     if (book) {
-        double e = block_sum_wave(eflux);
+        const double e = ewave;
         if ((t & 63) == 0) red[t >> 6] = e;
         __syncthreads();
         if (t == 0) {

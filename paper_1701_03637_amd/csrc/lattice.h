@@ -60,6 +60,53 @@ LBSC_HD bool in_sink(const Sink& s, int x, int y, int z, int nx, int ny, int nz)
     }
 }
 
+// Fluid z range of the column (x, y): nodes (x, y, z) with lo <= z <= hi lie
+// outside the sink, every other node of the column inside it. For all sink
+// kinds the fluid part of a column is one interval (for the sphere the
+// computed distance is monotone in |z - cz|), found here from a continuous
+// estimate and settled with the exact test of in_sink. Packed as
+// lo | hi << 16; an all-sink column is lo = 1, hi = 0.
+LBSC_HD uint32_t sink_zrange(const Sink& s, int x, int y, int nx, int ny, int nz)
+{
+    int lo = 0, hi = nz - 1;
+    switch (s.kind) {
+    case kSinkZmax: hi = nz - 2; break;
+    case kSinkFaces:
+        lo = 1;
+        hi = (x == 0 || y == 0 || x == nx - 1 || y == ny - 1) ? 0 : nz - 2;
+        break;
+    case kSinkSphere: {
+        const double dx = x - s.cx, dy = y - s.cy;
+        const double rem = s.r2 - (dx * dx + dy * dy);
+        const double h = rem > 0 ? sqrt(rem) : 0.0;
+        double zl = ceil(s.cz - h), zh = floor(s.cz + h);
+        zl = zl < 0 ? 0 : (zl > nz - 1 ? nz - 1 : zl);
+        zh = zh < 0 ? 0 : (zh > nz - 1 ? nz - 1 : zh);
+        lo = (int)zl;
+        hi = (int)zh;
+        if (lo > hi) {
+            double zc = floor(s.cz + 0.5);
+            zc = zc < 0 ? 0 : (zc > nz - 1 ? nz - 1 : zc);
+            lo = hi = (int)zc;
+        }
+        while (lo <= hi && in_sink(s, x, y, lo, nx, ny, nz)) ++lo;
+        while (hi >= lo && in_sink(s, x, y, hi, nx, ny, nz)) --hi;
+        if (lo > hi) {
+            lo = 1;
+            hi = 0;
+            break;
+        }
+        while (lo > 0 && !in_sink(s, x, y, lo - 1, nx, ny, nz)) --lo;
+        while (hi < nz - 1 && !in_sink(s, x, y, hi + 1, nx, ny, nz)) ++hi;
+        break;
+    }
+    default: break;
+    }
+    return (uint32_t)lo | ((uint32_t)hi << 16);
+}
+
+LBSC_HD bool in_zrange_sink(uint32_t zr, int z) { return z < (int)(zr & 0xffffu) || z > (int)(zr >> 16); }
+
 // Per-instance description, stored in device memory.
 struct Inst {
     int32_t nx, ny, nz, wall_z;

@@ -140,11 +140,13 @@ lbsc_status validate(const lbsc_params& p, int k, std::string& why)
 }
 
 // Work items of one instance for the schedule in `t` (see lbsc_tiles).
-void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int64_t total_nodes, std::vector<Item>& out)
+void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int64_t total_nodes, int target_items,
+                    std::vector<Item>& out)
 {
     // Defaults from tile sweeps on MI355X: rows as wide as possible (up to
-    // 128), and about 512 blocks per context with at least 16 planes per
-    // z chunk (each chunk re-derives the densities of two extra planes).
+    // 128), and about target_items blocks per context with at least 16
+    // planes per z chunk (each chunk re-derives the densities of two extra
+    // planes).
     int tw = t.tw > 0 ? t.tw : 128;
     tw = std::min({tw, I.nx, 128, nt});
     int th = t.th > 0 ? t.th : std::max(1, nt / tw);
@@ -153,7 +155,7 @@ void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int64_
     const int cols = mx * my;
     int nzc = t.nzc;
     if (nzc <= 0) {
-        double want = 512.0 * (double)I.n / (double)total_nodes / cols;
+        double want = (double)target_items * (double)I.n / (double)total_nodes / cols;
         int chunks = std::max(1, (int)std::ceil(want));
         chunks = std::min(chunks, std::max(1, I.nz / 16));
         nzc = (I.nz + chunks - 1) / chunks;
@@ -177,7 +179,11 @@ void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int64_
 lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& items, std::vector<Inst>& inst, int& nt,
                         int& variant)
 {
-    nt = t.nt > 0 ? t.nt : 256;
+    // FP32-arithmetic forms run 512-thread blocks and many short chunks by
+    // default, FP64 (register-bound at two waves per SIMD) 256-thread blocks.
+    const bool f64 = c->precision == LBSC_FP64;
+    nt = t.nt > 0 ? t.nt : (f64 ? 256 : 512);
+    const int target_items = f64 ? 256 : 4096;
     if (nt != 256 && nt != 512) return fail(c, LBSC_E_ARG, "tiles.nt must be 256 or 512");
     if (t.variant > 3) return fail(c, LBSC_E_ARG, "tiles.variant must be 0, 1, 2 or 3");
     if (t.variant == 3 && (c->precision == LBSC_FP64 || c->precision == LBSC_FP16N))
@@ -188,7 +194,7 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
     items.clear();
     for (int k = 0; k < (int)inst.size(); ++k) {
         inst[k].item_begin = (int32_t)items.size();
-        instance_items(inst[k], k, t, nt, total, items);
+        instance_items(inst[k], k, t, nt, total, target_items, items);
         inst[k].item_end = (int32_t)items.size();
     }
     if (items.size() > c->max_items)
@@ -853,6 +859,43 @@ lbsc_status lbsc_stream_copy(void* dst, const void* src, size_t bytes, void* hip
     return hipGetLastError() == hipSuccess ? LBSC_OK : LBSC_E_HIP;
 }
 
+// Pipelined-step halo check of one tile: every stencil read of every tile
+// node lands on a footprint cell that the block writes (a tile node or one of
+// its nring <= nt halo nodes) and that cell holds the right lattice node.
+int pipe_halo_errors(const Item& it, int nx, int ny, int nt)
+{
+    const int tw = it.tw, th = it.th, row = tw + 2;
+    const bool xper = tw == nx, yper = th == ny;
+    const lbsc::PipeTile p = lbsc::pipe_tile(tw, th, nx, ny);
+    if (p.nring > nt) return 0;  // the pipelined step rejects this tile
+    std::vector<int> cell((size_t)row * (th + 2), -1);  // lattice node in each written cell
+    auto node = [&](int fx, int fy) { return lbsc::wrap(it.y0 + fy, ny) * nx + lbsc::wrap(it.x0 + fx, nx); };
+    int bad = 0;
+    for (int ty = 0; ty < th; ++ty)
+        for (int tx = 0; tx < tw; ++tx) cell[(size_t)(ty + 1) * row + tx + 1] = node(tx, ty);
+    for (int r = 0; r < p.nring; ++r) {
+        int fx, fy;
+        lbsc::pipe_ring_node(r, p, tw, th, xper, fx, fy);
+        if (fx < -1 || fx > tw || fy < -1 || fy > th) { ++bad; continue; }
+        int& c = cell[(size_t)(fy + 1) * row + fx + 1];
+        if (c != -1) ++bad;  // each cell written once
+        c = node(fx, fy);
+    }
+    for (int ty = 0; ty < th; ++ty)
+        for (int tx = 0; tx < tw; ++tx) {
+            int cI[3], rI[3];
+            lbsc::pipe_stencil(tx, tw, xper, cI);
+            lbsc::pipe_stencil(ty, th, yper, rI);
+            for (int ey = -1; ey <= 1; ++ey)
+                for (int ex = -1; ex <= 1; ++ex) {
+                    const int ci = cI[1 + ex], ri = rI[1 + ey];
+                    if (ci < 0 || ci > tw + 1 || ri < 0 || ri > th + 1) { ++bad; continue; }
+                    if (cell[(size_t)ri * row + ci] != node(tx + ex, ty + ey)) ++bad;
+                }
+        }
+    return bad;
+}
+
 int32_t lbsc_selftest(void)
 {
     using namespace lbsc;
@@ -925,17 +968,48 @@ int32_t lbsc_selftest(void)
                 const int p = psi_plane(z, nz, wall);
                 if (p < 0 || p >= nz) ++bad;
             }
+    // The packed fluid z interval of every column reproduces in_sink node by
+    // node (spheres with random, half-integer and outside centres, radii with
+    // exact ties; the other kinds).
+    {
+        uint64_t st = 0x9E3779B97F4A7C15ull;
+        auto rnd = [&]() {
+            st = st * 6364136223846793005ull + 1442695040888963407ull;
+            return (double)(st >> 11) * (1.0 / 9007199254740992.0);
+        };
+        const int dims2[][3] = {{13, 11, 17}, {7, 9, 40}, {5, 5, 3}, {1, 1, 9}};
+        for (auto& d : dims2)
+            for (int trial = 0; trial < 60; ++trial) {
+                Sink sk{};
+                sk.kind = trial < 3 ? trial : kSinkSphere;
+                const int mode = trial % 4;
+                auto coord = [&](int n) {
+                    const double u = rnd() * (n + 6) - 3;
+                    return mode == 0 ? u : (mode == 1 ? std::floor(u) + 0.5 : (mode == 2 ? std::floor(u) : u * 3));
+                };
+                sk.cx = coord(d[0]); sk.cy = coord(d[1]); sk.cz = coord(d[2]);
+                const double r = rnd() * 0.8 * (d[0] + d[1] + d[2]) / 2;
+                sk.r2 = mode == 2 ? std::floor(r * r) : r * r;
+                for (int y = 0; y < d[1]; ++y)
+                    for (int x = 0; x < d[0]; ++x) {
+                        const uint32_t zr = sink_zrange(sk, x, y, d[0], d[1], d[2]);
+                        for (int z = 0; z < d[2]; ++z)
+                            if (in_zrange_sink(zr, z) != in_sink(sk, x, y, z, d[0], d[1], d[2])) ++bad;
+                    }
+            }
+    }
     // Work items tile every lattice exactly once.
     const int dims[][3] = {{4, 4, 128}, {128, 128, 128}, {48, 48, 48}, {156, 156, 156}, {1, 1, 64}, {200, 7, 9}};
     for (auto& d : dims)
         for (int nt : {256, 512})
             for (int tw : {0, 8, 16, 32, 64, 128})
-                for (int nzc : {0, 4, 16}) {
+                for (int nzc : {0, 4, 16})
+                for (int target : {256, 4096}) {
                     Inst I{};
                     I.nx = d[0]; I.ny = d[1]; I.nz = d[2];
                     I.n = (int64_t)d[0] * d[1] * d[2];
                     std::vector<Item> items;
-                    instance_items(I, 0, lbsc_tiles{nt, tw, 0, nzc, 0}, nt, I.n, items);
+                    instance_items(I, 0, lbsc_tiles{nt, tw, 0, nzc, 0}, nt, I.n, target, items);
                     std::vector<unsigned char> cover((size_t)I.n, 0);
                     for (auto& it : items) {
                         if (it.tw * it.th > nt || it.tw > 128 || it.th > 128) ++bad;
@@ -950,6 +1024,7 @@ int32_t lbsc_selftest(void)
                     }
                     for (auto v : cover)
                         if (v != 1) { ++bad; break; }
+                    for (auto& it : items) bad += pipe_halo_errors(it, I.nx, I.ny, nt);
                 }
     return bad;
 }

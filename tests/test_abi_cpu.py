@@ -98,10 +98,10 @@ def test_kernel_variant_resolution(lib):
         lib.lbsc_destroy(h)
         return rc, out.nt, out.variant
 
-    assert resolve("fp32s", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 256, 3)
-    assert resolve("fp16s", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 256, 3)
+    assert resolve("fp32s", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 512, 3)
+    assert resolve("fp16s", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 512, 3)
     assert resolve("fp64", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 256, 1)
-    assert resolve("fp16n", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 256, 1)
+    assert resolve("fp16n", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 512, 1)
     # 128 x 2 tiles of a 256-wide lattice: 2 (128 + 2) + 2 x 2 = 264 halo nodes
     assert resolve("fp32s", (256, 64, 32), (256, 128, 2, 0, 0)) == (0, 256, 1)
     rc, _, _ = resolve("fp32s", (256, 64, 32), (256, 128, 2, 0, 3))
