@@ -30,6 +30,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lattice.h"
 
 namespace lbsc {
@@ -152,37 +154,71 @@ template <class S> struct RawNode<S, true> {
     typename S::T h[2][kQ];
 };
 
-// Issues the loads of the pull of node (x, y, z): population i from
-// x - e_i, or the reflected population across a wall on the z seam.
+// Source of each population of the pull of node (x, y, z): population i
+// comes from x - e_i, or is the reflected population of the node itself
+// across a wall on the z seam. z is block-uniform for every pull, so the
+// slab resources and the wall branch are scalar.
+template <class S>
+struct PullAddr {
+    Rsrc sl[3];             // slabs z-1, z, z+1
+    uint32_t xs[3], ys[3];  // x-1, x, x+1 and (y-1, y, y+1) * nx
+    bool wall_lo, wall_hi;
+    uint32_t ps;
+
+    __device__ __forceinline__ PullAddr(const typename S::T* __restrict__ src, const Inst& I, int x, int y, int z)
+    {
+        const int nx = I.nx, ny = I.ny, nz = I.nz;
+        xs[0] = (uint32_t)wrap(x - 1, nx); xs[1] = (uint32_t)x; xs[2] = (uint32_t)wrap(x + 1, nx);
+        ys[0] = (uint32_t)(wrap(y - 1, ny) * nx); ys[1] = (uint32_t)(y * nx); ys[2] = (uint32_t)(wrap(y + 1, ny) * nx);
+        wall_lo = I.wall_z && z == 0;
+        wall_hi = I.wall_z && z == nz - 1;
+        sl[0] = slab_rsrc(src + (int64_t)wrap(z - 1, nz) * I.slab);
+        sl[1] = slab_rsrc(src + (int64_t)z * I.slab);
+        sl[2] = slab_rsrc(src + (int64_t)wrap(z + 1, nz) * I.slab);
+        ps = (uint32_t)I.ps;
+    }
+    __device__ __forceinline__ bool refl(int i) const { return (ez(i) > 0 && wall_lo) || (ez(i) < 0 && wall_hi); }
+    __device__ __forceinline__ int q(int i) const { return refl(i) ? opp(i) : i; }
+    __device__ __forceinline__ Rsrc rsrc(int i) const { return refl(i) ? sl[1] : sl[1 - ez(i)]; }
+    __device__ __forceinline__ uint32_t xy(int i) const
+    {
+        return refl(i) ? ys[1] + xs[1] : ys[1 - ey(i)] + xs[1 - ex(i)];
+    }
+};
+
+// Loads of the pull of node (x, y, z) for storage without a per-node rest
+// encoding, straight into v.
+template <class S>
+__device__ __forceinline__ void pull_vals(const typename S::T* __restrict__ src, const Inst& I, int x, int y, int z,
+                                          typename S::T (&v)[2][kQ])
+{
+    using T = typename S::T;
+    static_assert(!S::kNode, "per-node encodings load through RawNode");
+    const PullAddr<S> a(src, I, x, y, z);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+            v[c][i] = bload<T>(a.rsrc(i), a.xy(i) * (uint32_t)sizeof(T), plane_off<S>(c, a.q(i), a.ps));
+}
+
+// Issues the loads of the pull of node (x, y, z) into a raw set.
 template <class S>
 __device__ __forceinline__ void pull_raw(const typename S::T* __restrict__ src, const Inst& I, int x, int y, int z,
                                          RawNode<S>& w)
 {
     using T = typename S::T;
-    const int nx = I.nx, ny = I.ny, nz = I.nz;
-    const uint32_t xs[3] = {(uint32_t)wrap(x - 1, nx), (uint32_t)x, (uint32_t)wrap(x + 1, nx)};
-    const uint32_t ys[3] = {(uint32_t)(wrap(y - 1, ny) * nx), (uint32_t)(y * nx), (uint32_t)(wrap(y + 1, ny) * nx)};
-    // z is block-uniform for every call, so the resources and the wall
-    // branch are scalar.
-    const bool wall_lo = I.wall_z && z == 0, wall_hi = I.wall_z && z == nz - 1;
-    const Rsrc sl[3] = {slab_rsrc(src + (int64_t)wrap(z - 1, nz) * I.slab), slab_rsrc(src + (int64_t)z * I.slab),
-                        slab_rsrc(src + (int64_t)wrap(z + 1, nz) * I.slab)};
-    const uint32_t ps = (uint32_t)I.ps;
+    if constexpr (S::kNode) {
+        const PullAddr<S> a(src, I, x, y, z);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        const bool refl = (ez(i) > 0 && wall_lo) || (ez(i) < 0 && wall_hi);
-        const int q = refl ? opp(i) : i;
-        const Rsrc r = refl ? sl[1] : sl[1 - ez(i)];
-        const uint32_t xy = refl ? ys[1] + xs[1] : ys[1 - ey(i)] + xs[1 - ex(i)];
+        for (int i = 0; i < kQ; ++i)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            if constexpr (S::kNode) {
-                w.d0[c][i] = bload<float>(r, xy * 4u, plane_off<S>(c, 0, ps));
-                if (i != 0) w.h[c][i] = bload<T>(r, xy * 2u, plane_off<S>(c, q, ps));
-            } else {
-                w.v[c][i] = bload<T>(r, xy * (uint32_t)sizeof(T), plane_off<S>(c, q, ps));
+            for (int c = 0; c < 2; ++c) {
+                w.d0[c][i] = bload<float>(a.rsrc(i), a.xy(i) * 4u, plane_off<S>(c, 0, a.ps));
+                if (i != 0) w.h[c][i] = bload<T>(a.rsrc(i), a.xy(i) * 2u, plane_off<S>(c, a.q(i), a.ps));
             }
-        }
+    } else {
+        pull_vals<S>(src, I, x, y, z, w.v);
     }
 }
 
@@ -302,6 +338,11 @@ __device__ __forceinline__ double sink_reset(const Inst& I, NodeVals<A>& v)
 // S[c] = sum_{i>0} w_i psi^{cbar}(x + e_i) e_i, the neighbour sum of Eq. (sc).
 // ---------------------------------------------------------------------------
 
+// 1/x: IEEE division in FP64, the hardware reciprocal (1 ulp) in FP32.
+template <typename A> __device__ __forceinline__ A recip(A x);
+template <> __device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
+template <> __device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
 template <typename A>
 __device__ __forceinline__ void collide_node(const Inst& I, NodeVals<A>& v, const A S[2][3], A psiA, A psiB)
 {
@@ -319,18 +360,18 @@ __device__ __forceinline__ void collide_node(const Inst& I, NodeVals<A>& v, cons
     }
     // u' = sum_c j^c / sum_c rho^c; the force shift tau^c F^c / rho^c with
     // F^c = -psi^c g S^c is applied as u^c = u' + k^c S^c.
-    const A inv_rt = (A)1 / (v.rho[0] + v.rho[1]);
+    const A inv_rt = recip<A>(v.rho[0] + v.rho[1]);
     const A up[3] = {(j[0][0] + j[1][0]) * inv_rt, (j[0][1] + j[1][1]) * inv_rt, (j[0][2] + j[1][2]) * inv_rt};
     const A psi[2] = {psiA, psiB};
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const A tau = (A)I.tau[c];
         const A rho = v.rho[c];
-        const A kc = rho != (A)0 ? -tau * (A)I.g * psi[c] / rho : (A)0;
+        const A kc = rho != (A)0 ? -tau * (A)I.g * psi[c] * recip<A>(rho) : (A)0;
         const A u[3] = {up[0] + kc * S[c][0], up[1] + kc * S[c][1], up[2] + kc * S[c][2]};
         const A uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
         const A drho = v.drho[c];
-        const A omega = (A)1 / tau;
+        const A omega = (A)I.omega[c];
         // Rest: f^eq_0 = w_0 (drho + rho (-1.5 u.u)) in deviation form.
         const A base0 = drho - (A)1.5 * rho * uu;
         v.f[c][0] = v.f[c][0] - (v.f[c][0] - (A)wgt(0) * base0) * omega;
@@ -603,12 +644,17 @@ __host__ __device__ inline void pipe_stencil(int a, int w, bool per, int out[3])
 }
 
 template <class St, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_step_pipe(const Inst* __restrict__ insts, const Item* __restrict__ items,
-                                                  int n_items, const typename St::T* __restrict__ src,
-                                                  typename St::T* __restrict__ dst, double* __restrict__ eacc)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_step_pipe(
+    const Inst* __restrict__ insts, const Item* __restrict__ items, int n_items, const typename St::T* __restrict__ src,
+    typename St::T* __restrict__ dst, double* __restrict__ eacc)
 {
     using T = typename St::T;
     using A = typename St::A;
+    // Storage in the arithmetic type (FP32S): decoding is the identity, so a
+    // plane loads straight into the population set its collision uses, and
+    // three sets rotate (collided / decoded / in flight). Otherwise the loads
+    // land in a raw set that is decoded into one of two sets.
+    constexpr bool kRotate = std::is_same_v<T, A> && !St::kNode;
     constexpr int FP = Foot<NT>::kMax;
     __shared__ A psiS[4][2][FP];
     __shared__ double red[NT / 64];
@@ -653,21 +699,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     // per-lane accumulator occupies registers across the march.
     double ewave = 0.0;
 
-    RawNode<St> ro, rr;
-    NodeVals<A> va, vb;
-
-    auto issue_into = [&](int zq, RawNode<St>& wo, RawNode<St>& wr) {
-        const int zp = psi_plane(zq, I.nz, I.wall_z);
-        if (ring) pull_raw<St>(s, I, hx, hy, zp, wr);
-        if (own) pull_raw<St>(s, I, x, y, zp, wo);
+    // Loads of logical plane zq: the halo node into wr, the tile node into wo.
+    auto issue_ring = [&](int zq, RawNode<St>& wr) {
+        if (ring) pull_raw<St>(s, I, hx, hy, psi_plane(zq, I.nz, I.wall_z), wr);
     };
-    auto issue = [&](int zq) { issue_into(zq, ro, rr); };
-    // Densities (with the pull-time sink reset) of logical plane zq from the
-    // issued loads; psi to its LDS slot, the tile node's values to keep.
-    auto dens_from = [&](int zq, NodeVals<A>& keep, const RawNode<St>& wo, const RawNode<St>& wr) {
+    auto issue_own = [&](int zq, T (&wo)[2][kQ]) {
+        if (own) pull_vals<St>(s, I, x, y, psi_plane(zq, I.nz, I.wall_z), wo);
+    };
+    // Densities (with the pull-time sink reset) of logical plane zq: psi of
+    // the halo node from wr and of the tile node from v (decoded, reset in
+    // place) into the plane's LDS slot; the flux of reset tile nodes is
+    // booked.
+    auto dens = [&](int zq, const RawNode<St>& wr, NodeVals<A>& v) {
         const int zp = psi_plane(zq, I.nz, I.wall_z);
-        double fl = 0.0;
         A(*ps)[FP] = psiS[(zq - z0 + 1) & 3];
+        double fl = 0.0;
         if (ring) {
             NodeVals<A> h;
             decode_raw<St>(wr, h);
@@ -677,17 +723,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             ps[1][fh] = psi_of<A>(h.rho[1], I.psi_exp);
         }
         if (own) {
-            decode_raw<St>(wo, keep);
-            node_density<A>(I, keep);
-            if (in_zrange_sink(zr_own, zp)) fl = sink_reset<A>(I, keep);
-            ps[0][fo] = psi_of<A>(keep.rho[0], I.psi_exp);
-            ps[1][fo] = psi_of<A>(keep.rho[1], I.psi_exp);
+            node_density<A>(I, v);
+            if (in_zrange_sink(zr_own, zp)) fl = sink_reset<A>(I, v);
+            ps[0][fo] = psi_of<A>(v.rho[0], I.psi_exp);
+            ps[1][fo] = psi_of<A>(v.rho[1], I.psi_exp);
         }
-        if (book && zq >= z0 && zq < z1 && __builtin_amdgcn_ballot_w64(fl != 0.0)) {
+        if (book && zq >= z0 && zq < z1 && __builtin_amdgcn_ballot_w64(fl != 0.0))
             ewave = wave_uniform(ewave + block_sum_wave(fl));
-        }
     };
-    auto dens = [&](int zq, NodeVals<A>& keep) { dens_from(zq, keep, ro, rr); };
     auto collide = [&](int z, NodeVals<A>& v) {
         if (!own) return;
         const uint32_t xy = (uint32_t)y * (uint32_t)I.nx + (uint32_t)x;
@@ -699,31 +742,81 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         store_node<St>(d, I, z, xy, v);
     };
 
-    // Prologue: two planes in flight at a time (the second pair of raw sets
-    // is dead before the loop's working set is live).
-    {
-        RawNode<St> ro2, rr2;
-        issue_into(z0 - 1, ro2, rr2);
-        issue(z0);
-        dens_from(z0 - 1, va, ro2, rr2);
-        issue_into(z0 + 1, ro2, rr2);
-        dens(z0, va);
-        if (z0 + 2 <= z1) issue(z0 + 2);
-        dens_from(z0 + 1, vb, ro2, rr2);
-    }
-    for (int z = z0; z < z1; z += 2) {
-        __syncthreads();
-        collide(z, va);
-        if (z + 2 <= z1) {
-            dens(z + 2, va);
-            if (z + 3 <= z1) issue(z + 3);
+    if constexpr (kRotate) {
+        NodeVals<A> p0, p1, p2;
+        RawNode<St> rr;
+        // Prologue: two planes in flight at a time.
+        {
+            RawNode<St> rr2;
+            issue_ring(z0 - 1, rr);
+            issue_own(z0 - 1, p2.f);
+            issue_ring(z0, rr2);
+            issue_own(z0, p0.f);
+            dens(z0 - 1, rr, p2);
+            issue_ring(z0 + 1, rr);
+            issue_own(z0 + 1, p1.f);
+            dens(z0, rr2, p0);
         }
-        if (z + 1 < z1) {
+        dens(z0 + 1, rr, p1);
+        if (z0 + 2 <= z1) {
+            issue_ring(z0 + 2, rr);
+            issue_own(z0 + 2, p2.f);
+        }
+        // Plane z collides from a; plane z+2 (loaded into c) is reduced to
+        // densities; plane z+3 loads into a.
+        auto step = [&](int z, NodeVals<A>& a, NodeVals<A>& c) {
             __syncthreads();
-            collide(z + 1, vb);
-            if (z + 3 <= z1) {
-                dens(z + 3, vb);
-                if (z + 4 <= z1) issue(z + 4);
+            collide(z, a);
+            if (z + 2 <= z1) {
+                dens(z + 2, rr, c);
+                if (z + 3 <= z1) {
+                    issue_ring(z + 3, rr);
+                    issue_own(z + 3, a.f);
+                }
+            }
+        };
+        for (int z = z0; z < z1; z += 3) {
+            step(z, p0, p2);
+            if (z + 1 < z1) step(z + 1, p1, p0);
+            if (z + 2 < z1) step(z + 2, p2, p1);
+        }
+    } else {
+        RawNode<St> ro, rr;
+        NodeVals<A> va, vb;
+        auto issue_into = [&](int zq, RawNode<St>& wo, RawNode<St>& wr) {
+            issue_ring(zq, wr);
+            if (own) pull_raw<St>(s, I, x, y, psi_plane(zq, I.nz, I.wall_z), wo);
+        };
+        auto dens_from = [&](int zq, NodeVals<A>& keep, const RawNode<St>& wo, const RawNode<St>& wr) {
+            if (own) decode_raw<St>(wo, keep);
+            dens(zq, wr, keep);
+        };
+        // Prologue: two planes in flight at a time (the second pair of raw
+        // sets is dead before the loop's working set is live).
+        {
+            RawNode<St> ro2, rr2;
+            issue_into(z0 - 1, ro2, rr2);
+            issue_into(z0, ro, rr);
+            dens_from(z0 - 1, va, ro2, rr2);
+            issue_into(z0 + 1, ro2, rr2);
+            dens_from(z0, va, ro, rr);
+            if (z0 + 2 <= z1) issue_into(z0 + 2, ro, rr);
+            dens_from(z0 + 1, vb, ro2, rr2);
+        }
+        for (int z = z0; z < z1; z += 2) {
+            __syncthreads();
+            collide(z, va);
+            if (z + 2 <= z1) {
+                dens_from(z + 2, va, ro, rr);
+                if (z + 3 <= z1) issue_into(z + 3, ro, rr);
+            }
+            if (z + 1 < z1) {
+                __syncthreads();
+                collide(z + 1, vb);
+                if (z + 3 <= z1) {
+                    dens_from(z + 3, vb, ro, rr);
+                    if (z + 4 <= z1) issue_into(z + 4, ro, rr);
+                }
             }
         }
     }

@@ -117,6 +117,7 @@ struct Inst {
     int64_t slab;          // elements per z-slab: 2*19 planes
     int64_t base;          // element offset of this instance in the arena
     double tau[2];
+    double omega[2];       // 1 / tau
     double g;
     double shift[2];       // rho0^c of shifted storage (0 for plain FP64)
     double phi_in, phi_out;

@@ -405,6 +405,7 @@ lbsc_status lbsc_create(int32_t n_inst, const lbsc_params* params, lbsc_ctx** ou
         I.base = (int64_t)off;
         off = align_up(off + (size_t)p.nz * (size_t)I.slab, 256);
         I.tau[0] = p.tau[0]; I.tau[1] = p.tau[1];
+        I.omega[0] = 1.0 / p.tau[0]; I.omega[1] = 1.0 / p.tau[1];
         I.g = p.g;
         I.shift[0] = c->precision == LBSC_FP64 ? 0.0 : p.shift[0];
         I.shift[1] = c->precision == LBSC_FP64 ? 0.0 : p.shift[1];
