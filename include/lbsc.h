@@ -114,7 +114,7 @@ typedef struct lbsc_diag {
 typedef struct lbsc_ctx lbsc_ctx;
 
 /* Tile schedule of the fused step kernel: nt threads per block (256 or 512),
- * xy tile tw x th (tw, th <= 128, tw*th <= nt), z chunk of nzc planes, and the
+ * xy tile tw x th (tw*th <= nt), z chunk of nzc planes, and the
  * kernel variant: 1 keeps a node's pulled populations in registers from its
  * density pass to its collision, 2 pulls the node again for the collision
  * (fewer registers, more blocks per CU), 3 (FP32S / FP16S storage only) also

@@ -428,9 +428,8 @@ __device__ __forceinline__ void force_sum(const A (*pm)[FP], const A (*p0)[FP], 
 
 template <int NT> struct Foot {
     // Largest (tw + 2)(th + 2) = tw*th + 2(tw + th) + 4 over tiles with
-    // tw*th <= NT and tw, th <= min(NT, 128): tw + th peaks at the extremes.
-    static constexpr int kSide = NT < 128 ? NT : 128;
-    static constexpr int kMax = NT + 2 * (kSide + NT / kSide) + 4;
+    // tw*th <= NT and tw, th <= NT: tw + th peaks at the extremes (NT x 1).
+    static constexpr int kMax = 3 * NT + 6;
 };
 
 __device__ __forceinline__ void ring_coord(int r, int tw, int th, int& fx, int& fy)

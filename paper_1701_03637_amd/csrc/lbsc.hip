@@ -140,38 +140,68 @@ lbsc_status validate(const lbsc_params& p, int k, std::string& why)
 }
 
 // Work items of one instance for the schedule in `t` (see lbsc_tiles).
+// Split [0, n) into parts: fixed width w with a ragged last part, or, with
+// w <= 0, `parts` near-equal parts (sizes differ by at most one).
+std::vector<int> split_range(int n, int w, int parts)
+{
+    std::vector<int> b;
+    if (w > 0) {
+        for (int a = 0; a < n; a += w) b.push_back(a);
+    } else {
+        for (int k = 0; k < parts; ++k) b.push_back((int)((int64_t)k * n / parts));
+    }
+    b.push_back(n);
+    return b;
+}
+
 void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int64_t total_nodes, int target_items,
                     std::vector<Item>& out)
 {
-    // Defaults from tile sweeps on MI355X: rows as wide as possible (up to
-    // 128), and about target_items blocks per context with at least 16
+    // Defaults from tile sweeps on MI355X: a tile spans the whole x extent
+    // while its two halo rows fit the block (nx <= nt / 2: contiguous reads,
+    // no x halo), else x splits evenly into parts of at most 128; as many
+    // rows as the block holds, split evenly so that no block runs a thin
+    // ragged tile; about target_items blocks per context with at least 16
     // planes per z chunk (each chunk re-derives the densities of two extra
-    // planes).
-    int tw = t.tw > 0 ? t.tw : 128;
-    tw = std::min({tw, I.nx, 128, nt});
-    int th = t.th > 0 ? t.th : std::max(1, nt / tw);
-    th = std::min({th, I.ny, 128, std::max(1, nt / tw)});
-    const int mx = (I.nx + tw - 1) / tw, my = (I.ny + th - 1) / th;
-    const int cols = mx * my;
-    int nzc = t.nzc;
-    if (nzc <= 0) {
+    // planes). Explicit tw / th / nzc give fixed sizes with a ragged last
+    // tile.
+    const int cap = std::min(128, nt);
+    std::vector<int> xb, yb, zb;
+    if (t.tw > 0) {
+        xb = split_range(I.nx, std::min({t.tw, I.nx, nt}), 0);
+    } else if (I.nx <= nt / 2) {
+        xb = split_range(I.nx, 0, 1);
+    } else {
+        xb = split_range(I.nx, 0, (I.nx + cap - 1) / cap);
+    }
+    int twmax = 0;
+    for (size_t k = 0; k + 1 < xb.size(); ++k) twmax = std::max(twmax, xb[k + 1] - xb[k]);
+    const int thcap = std::min(I.ny, std::max(1, nt / twmax));
+    if (t.th > 0) {
+        yb = split_range(I.ny, std::min(t.th, thcap), 0);
+    } else {
+        yb = split_range(I.ny, 0, (I.ny + thcap - 1) / thcap);
+    }
+    const int cols = (int)((xb.size() - 1) * (yb.size() - 1));
+    if (t.nzc > 0) {
+        zb = split_range(I.nz, std::min(t.nzc, I.nz), 0);
+    } else {
         double want = (double)target_items * (double)I.n / (double)total_nodes / cols;
         int chunks = std::max(1, (int)std::ceil(want));
         chunks = std::min(chunks, std::max(1, I.nz / 16));
-        nzc = (I.nz + chunks - 1) / chunks;
+        zb = split_range(I.nz, 0, chunks);
     }
-    nzc = std::min(nzc, I.nz);
-    for (int z0 = 0; z0 < I.nz; z0 += nzc)
-        for (int by = 0; by < my; ++by)
-            for (int bx = 0; bx < mx; ++bx) {
+    for (size_t kz = 0; kz + 1 < zb.size(); ++kz)
+        for (size_t ky = 0; ky + 1 < yb.size(); ++ky)
+            for (size_t kx = 0; kx + 1 < xb.size(); ++kx) {
                 Item it{};
                 it.inst = inst;
-                it.x0 = (int16_t)(bx * tw);
-                it.y0 = (int16_t)(by * th);
-                it.tw = (int16_t)std::min(tw, I.nx - bx * tw);
-                it.th = (int16_t)std::min(th, I.ny - by * th);
-                it.z0 = (int16_t)z0;
-                it.nzc = (int16_t)std::min(nzc, I.nz - z0);
+                it.x0 = (int16_t)xb[kx];
+                it.y0 = (int16_t)yb[ky];
+                it.tw = (int16_t)(xb[kx + 1] - xb[kx]);
+                it.th = (int16_t)(yb[ky + 1] - yb[ky]);
+                it.z0 = (int16_t)zb[kz];
+                it.nzc = (int16_t)(zb[kz + 1] - zb[kz]);
                 out.push_back(it);
             }
 }
@@ -188,7 +218,7 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
     if (t.variant > 3) return fail(c, LBSC_E_ARG, "tiles.variant must be 0, 1, 2 or 3");
     if (t.variant == 3 && (c->precision == LBSC_FP64 || c->precision == LBSC_FP16N))
         return fail(c, LBSC_E_ARG, "tiles.variant 3 needs FP32S or FP16S storage");
-    if (t.tw > 128 || t.th > 128) return fail(c, LBSC_E_ARG, "tiles.tw and tiles.th must be <= 128");
+    if (t.tw > 512 || t.th > 512) return fail(c, LBSC_E_ARG, "tiles.tw and tiles.th must be <= 512");
     int64_t total = 0;
     for (auto& I : inst) total += I.n;
     items.clear();
@@ -203,7 +233,7 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
     const int foot = nt == 256 ? lbsc::Foot<256>::kMax : lbsc::Foot<512>::kMax;
     bool pipe_fits = c->precision == LBSC_FP32S || c->precision == LBSC_FP16S;
     for (auto& it : items) {
-        if (it.tw * it.th > nt || it.tw > 128 || it.th > 128 || (it.tw + 2) * (it.th + 2) > foot)
+        if (it.tw * it.th > nt || (it.tw + 2) * (it.th + 2) > foot)
             return fail(c, LBSC_E_ARG, "internal: tile %dx%d does not fit %d threads", it.tw, it.th, nt);
         const Inst& I = inst[it.inst];
         if (it.x0 < 0 || it.y0 < 0 || it.z0 < 0 || it.x0 + it.tw > I.nx || it.y0 + it.th > I.ny ||
@@ -1003,7 +1033,7 @@ int32_t lbsc_selftest(void)
     const int dims[][3] = {{4, 4, 128}, {128, 128, 128}, {48, 48, 48}, {156, 156, 156}, {1, 1, 64}, {200, 7, 9}};
     for (auto& d : dims)
         for (int nt : {256, 512})
-            for (int tw : {0, 8, 16, 32, 64, 128})
+            for (int tw : {0, 8, 16, 32, 64, 128, 200, 256})
                 for (int nzc : {0, 4, 16})
                 for (int target : {256, 4096}) {
                     Inst I{};
@@ -1013,7 +1043,7 @@ int32_t lbsc_selftest(void)
                     instance_items(I, 0, lbsc_tiles{nt, tw, 0, nzc, 0}, nt, I.n, target, items);
                     std::vector<unsigned char> cover((size_t)I.n, 0);
                     for (auto& it : items) {
-                        if (it.tw * it.th > nt || it.tw > 128 || it.th > 128) ++bad;
+                        if (it.tw * it.th > nt) ++bad;
                         const int foot = nt == 256 ? Foot<256>::kMax : Foot<512>::kMax;
                         if ((it.tw + 2) * (it.th + 2) > foot) ++bad;
                         for (int z = it.z0; z < it.z0 + it.nzc; ++z)

@@ -72,7 +72,7 @@ def test_tile_schedule_errors(lib):
     h = ctypes.c_void_p()
     p = lbsc.make_params(32, 32, 32)
     assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == 0
-    for t in (lbsc.Tiles(128, 0, 0, 0, 0), lbsc.Tiles(32, 16, 2, 0, 0), lbsc.Tiles(256, 200, 0, 0, 0), lbsc.Tiles(256, 0, 0, 0, 3)):
+    for t in (lbsc.Tiles(128, 0, 0, 0, 0), lbsc.Tiles(32, 16, 2, 0, 0), lbsc.Tiles(256, 600, 0, 0, 0), lbsc.Tiles(256, 0, 0, 0, 3)):
         assert lib.lbsc_set_tiles(h, ctypes.byref(t)) == -1
     assert lib.lbsc_set_tiles(h, ctypes.byref(lbsc.Tiles(512, 32, 16, 4, 2))) == 0
     nit = ctypes.c_int32()
@@ -109,3 +109,25 @@ def test_kernel_variant_resolution(lib):
     assert resolve("fp32s", (256, 64, 32), (512, 128, 4, 0, 3)) == (0, 512, 3)
     assert resolve("fp16n", (64, 64, 64), (256, 64, 4, 0, 3))[0] == -1
 
+
+
+def test_default_tiles_split_evenly(lib):
+    """Automatic schedules split x, y and z into near-equal parts: a 156^3
+    box gets full-width tiles of 3 rows (52 tiles; 156 = 3 x 52) in 9 chunks,
+    a 300-wide box three 100-wide tiles of 5 rows; the 128^3 droplet gets 32
+    tiles of 128 x 4 in 8 chunks of 16 planes."""
+    from paper_1701_03637_amd import lbsc
+
+    def items(n, prec):
+        h = ctypes.c_void_p()
+        p = lbsc.make_params(*n, precision=prec)
+        assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == 0
+        v = ctypes.c_int32()
+        assert lib.lbsc_num_items(h, ctypes.byref(v)) == 0
+        lib.lbsc_destroy(h)
+        return v.value
+
+    assert items((156, 156, 156), "fp32s") == 52 * 9
+    assert items((300, 40, 32), "fp32s") == 3 * 8 * 2
+    assert items((128, 128, 128), "fp32s") == 32 * 8
+    assert items((128, 128, 128), "fp64") == 64 * 4

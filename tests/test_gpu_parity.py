@@ -132,7 +132,8 @@ def test_fp64_droplet_ragged_tiles_and_sink_switch(lb):
 
 
 @pytest.mark.parametrize("tiles", [(256, 0, 0, 0, 1), (512, 0, 0, 0, 1), (256, 16, 4, 3, 1), (512, 32, 8, 7, 1),
-                                   (256, 64, 2, 5, 1), (256, 0, 0, 0, 2), (512, 32, 8, 7, 2), (256, 64, 2, 5, 2)])
+                                   (256, 64, 2, 5, 1), (256, 0, 0, 0, 2), (512, 32, 8, 7, 2), (256, 64, 2, 5, 2),
+                                   (256, 70, 3, 4, 1), (512, 256, 2, 6, 2)])
 @pytest.mark.parametrize("precision", ["fp64", "fp16n"])
 def test_tile_schedules_bitwise_identical(lb, tiles, precision):
     """The result does not depend on the tile schedule (catches LDS halo races
@@ -162,6 +163,9 @@ PIPE_CASES = [
     ((16, 8, 40), True, "zmax", (256, 16, 8, 1, 3)),
     ((40, 24, 21), False, "faces", (256, 32, 8, 2, 3)),
     ((128, 6, 9), False, "faces", (256, 128, 2, 0, 0)),
+    ((150, 7, 9), False, "faces", (512, 150, 3, 4, 3)),
+    ((150, 7, 9), False, "faces", (512, 0, 0, 0, 3)),
+    ((200, 5, 11), True, "zmax", (512, 200, 2, 0, 3)),
 ]
 
 
