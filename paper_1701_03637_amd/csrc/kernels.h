@@ -91,6 +91,21 @@ template <> __device__ __forceinline__ float psi_of<float>(float rho, int psi_ex
 // Pull of one node: 2 x 19 populations (delta form) and the sink reset.
 // ---------------------------------------------------------------------------
 
+// Per-instance constants in the arithmetic type: FP64 from the table's
+// doubles, FP32 from its host-rounded FP32 copies (identical values, but
+// scalar operands instead of per-lane conversions).
+template <typename A> struct Par;
+template <> struct Par<double> {
+    static __device__ __forceinline__ double shift(const Inst& I, int c) { return I.shift[c]; }
+    static __device__ __forceinline__ double omega(const Inst& I, int c) { return I.omega[c]; }
+    static __device__ __forceinline__ double ntg(const Inst& I, int c) { return -I.tau[c] * I.g; }
+};
+template <> struct Par<float> {
+    static __device__ __forceinline__ float shift(const Inst& I, int c) { return I.shift_f[c]; }
+    static __device__ __forceinline__ float omega(const Inst& I, int c) { return I.omega_f[c]; }
+    static __device__ __forceinline__ float ntg(const Inst& I, int c) { return I.ntg_f[c]; }
+};
+
 template <typename A>
 struct NodeVals {
     A f[2][kQ];
@@ -110,6 +125,8 @@ __device__ __forceinline__ Rsrc slab_rsrc(const void* p)
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, -1, 0x00020000);
 }
 
+// live = false: a resource with no records, so every access is out of
+// range and loads return zero without touching memory (stores are dropped).
 template <typename T> __device__ __forceinline__ T bload(Rsrc r, uint32_t voff, uint32_t soff);
 template <> __device__ __forceinline__ float bload<float>(Rsrc r, uint32_t voff, uint32_t soff)
 {
@@ -160,7 +177,7 @@ template <class S> struct RawNode<S, true> {
 // slab resources and the wall branch are scalar.
 template <class S>
 struct PullAddr {
-    Rsrc sl[3];             // slabs z-1, z, z+1
+    Rsrc sl[3];             // slabs read by e_z = +1, 0, -1
     uint32_t xs[3], ys[3];  // x-1, x, x+1 and (y-1, y, y+1) * nx
     bool wall_lo, wall_hi;
     uint32_t ps;
@@ -172,14 +189,21 @@ struct PullAddr {
         ys[0] = (uint32_t)(wrap(y - 1, ny) * nx); ys[1] = (uint32_t)(y * nx); ys[2] = (uint32_t)(wrap(y + 1, ny) * nx);
         wall_lo = I.wall_z && z == 0;
         wall_hi = I.wall_z && z == nz - 1;
-        sl[0] = slab_rsrc(src + (int64_t)wrap(z - 1, nz) * I.slab);
-        sl[1] = slab_rsrc(src + (int64_t)z * I.slab);
-        sl[2] = slab_rsrc(src + (int64_t)wrap(z + 1, nz) * I.slab);
+        // Directions with e_z = +1 read slab z-1, or slab z when they reflect
+        // off the wall below; e_z = -1 likewise with z+1. Choosing the slab
+        // pointer (not the resource) keeps every resource a plain scalar
+        // value.
+        const typename S::T* pz = src + (int64_t)z * I.slab;
+        const typename S::T* pm = wall_lo ? pz : src + (int64_t)wrap(z - 1, nz) * I.slab;
+        const typename S::T* pp = wall_hi ? pz : src + (int64_t)wrap(z + 1, nz) * I.slab;
+        sl[0] = slab_rsrc(pm);
+        sl[1] = slab_rsrc(pz);
+        sl[2] = slab_rsrc(pp);
         ps = (uint32_t)I.ps;
     }
     __device__ __forceinline__ bool refl(int i) const { return (ez(i) > 0 && wall_lo) || (ez(i) < 0 && wall_hi); }
     __device__ __forceinline__ int q(int i) const { return refl(i) ? opp(i) : i; }
-    __device__ __forceinline__ Rsrc rsrc(int i) const { return refl(i) ? sl[1] : sl[1 - ez(i)]; }
+    __device__ __forceinline__ Rsrc rsrc(int i) const { return sl[1 - ez(i)]; }
     __device__ __forceinline__ uint32_t xy(int i) const
     {
         return refl(i) ? ys[1] + xs[1] : ys[1 - ey(i)] + xs[1 - ex(i)];
@@ -287,7 +311,7 @@ __device__ __forceinline__ void node_density(const Inst& I, NodeVals<A>& v)
 #pragma unroll
         for (int i = 0; i < kQ; ++i) r += v.f[c][i];
         v.drho[c] = r;
-        v.rho[c] = (A)I.shift[c] + r;
+        v.rho[c] = Par<A>::shift(I, c) + r;
     }
 }
 
@@ -316,7 +340,11 @@ __device__ __forceinline__ double sink_reset(const Inst& I, NodeVals<A>& v)
     // rho_H - rho0^A is exact in FP64; the partner deviation
     // rhoB_H - rho0^B = (rho0^A - rho_H) + drho^A + drho^B is formed from
     // small terms, so no O(1) density is rounded.
-    const A da = (A)(rho_h - I.shift[0]);
+    A da = (A)(rho_h - I.shift[0]);
+    // The A reset is the same at every sink node; kept opaque so that it is
+    // formed here, at the (few) sink nodes, not hoisted out of the march
+    // into 19 registers.
+    asm volatile("" : "+v"(da));
     const A db = (A)(I.shift[0] - rho_h) + v.drho[0] + v.drho[1];
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
@@ -365,13 +393,12 @@ __device__ __forceinline__ void collide_node(const Inst& I, NodeVals<A>& v, cons
     const A psi[2] = {psiA, psiB};
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-        const A tau = (A)I.tau[c];
         const A rho = v.rho[c];
-        const A kc = rho != (A)0 ? -tau * (A)I.g * psi[c] * recip<A>(rho) : (A)0;
+        const A kc = rho != (A)0 ? Par<A>::ntg(I, c) * psi[c] * recip<A>(rho) : (A)0;
         const A u[3] = {up[0] + kc * S[c][0], up[1] + kc * S[c][1], up[2] + kc * S[c][2]};
         const A uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
         const A drho = v.drho[c];
-        const A omega = (A)I.omega[c];
+        const A omega = Par<A>::omega(I, c);
         // Rest: f^eq_0 = w_0 (drho + rho (-1.5 u.u)) in deviation form.
         const A base0 = drho - (A)1.5 * rho * uu;
         v.f[c][0] = v.f[c][0] - (v.f[c][0] - (A)wgt(0) * base0) * omega;
@@ -671,25 +698,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const bool xper = tw == I.nx, yper = th == I.ny;
     const PipeTile pt = pipe_tile(tw, th, I.nx, I.ny);
     const bool own = t < tw * th;
-    const int tx = own ? t % tw : 0;
-    const int ty = own ? t / tw : 0;
-    const int x = wrap(it.x0 + tx, I.nx);
-    const int y = wrap(it.y0 + ty, I.ny);
-    const int fo = (ty + 1) * row + tx + 1;
-    int cI[3], rI[3];
-    pipe_stencil(tx, tw, xper, cI);
-    pipe_stencil(ty, th, yper, rI);
-
-    // This thread's halo node.
     const bool ring = t < pt.nring;
-    int fx = 0, fy = 0;
-    if (ring) pipe_ring_node(t, pt, tw, th, xper, fx, fy);
-    const int hx = wrap(it.x0 + fx, I.nx), hy = wrap(it.y0 + fy, I.ny);
-    const int fh = (fy + 1) * row + fx + 1;
-    // Sink membership along the march: one packed z interval per column.
-    const uint32_t zr_own = sink_zrange(I.reset, x, y, I.nx, I.ny, I.nz);
-    const uint32_t zr_cur = sink_zrange(I.cur, x, y, I.nx, I.ny, I.nz);
-    const uint32_t zr_ring = sink_zrange(I.reset, hx, hy, I.nx, I.ny, I.nz);
+    // Per-thread coordinates and sink intervals live in LDS and are read
+    // where they are used: held in registers across the march they would
+    // crowd out the population sets, and the compiler would hoist the
+    // address arithmetic derived from them out of the march as well.
+    __shared__ uint32_t tinfo[7][NT];
+    {
+        const int tx = own ? t % tw : 0, ty = own ? t / tw : 0;
+        const int x = wrap(it.x0 + tx, I.nx), y = wrap(it.y0 + ty, I.ny);
+        int fx = 0, fy = 0;
+        if (ring) pipe_ring_node(t, pt, tw, th, xper, fx, fy);  // this thread's halo node
+        const int hx = wrap(it.x0 + fx, I.nx), hy = wrap(it.y0 + fy, I.ny);
+        auto pack = [](int a, int b) { return (uint32_t)a | ((uint32_t)b << 16); };
+        tinfo[0][t] = pack(x, y);
+        tinfo[1][t] = pack(hx, hy);
+        tinfo[2][t] = pack((ty + 1) * row + tx + 1, (fy + 1) * row + fx + 1);
+        tinfo[3][t] = pack(tx, ty);
+        // sink membership along the march: one packed z interval per column
+        tinfo[4][t] = sink_zrange(I.reset, x, y, I.nx, I.ny, I.nz);
+        tinfo[5][t] = sink_zrange(I.cur, x, y, I.nx, I.ny, I.nz);
+        tinfo[6][t] = sink_zrange(I.reset, hx, hy, I.nx, I.ny, I.nz);
+    }
+    auto lo = [](uint32_t v) { return (int)(v & 0xffffu); };
+    auto hi = [](uint32_t v) { return (int)(v >> 16); };
 
     const int z0 = it.z0, z1 = it.z0 + it.nzc;
     const bool book = I.count_reset != 0 && I.reset.kind != kSinkNone;
@@ -698,12 +730,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     // per-lane accumulator occupies registers across the march.
     double ewave = 0.0;
 
-    // Loads of logical plane zq: the halo node into wr, the tile node into wo.
+    // Loads of logical plane zq (none past the chunk's halo plane z1): the
+    // halo node into wr, the tile node into wo. Every step of the march
+    // reduces the plane loaded by the step before, on every path (planes past
+    // z1 reduce stale registers into a psi slot nothing reads), so no path
+    // carries a load past the point that consumes it and the compiler's
+    // memory waits stay exact. Every lane loads and reduces a tile node
+    // (lanes past the tile take the tile's first node, whose lines the tile
+    // lanes fetch anyway).
     auto issue_ring = [&](int zq, RawNode<St>& wr) {
-        if (ring) pull_raw<St>(s, I, hx, hy, psi_plane(zq, I.nz, I.wall_z), wr);
+        const uint32_t h = tinfo[1][t];
+        if (zq <= z1 && ring) pull_raw<St>(s, I, lo(h), hi(h), psi_plane(zq, I.nz, I.wall_z), wr);
     };
     auto issue_own = [&](int zq, T (&wo)[2][kQ]) {
-        if (own) pull_vals<St>(s, I, x, y, psi_plane(zq, I.nz, I.wall_z), wo);
+        const uint32_t o = tinfo[0][t];
+        if (zq <= z1) pull_vals<St>(s, I, lo(o), hi(o), psi_plane(zq, I.nz, I.wall_z), wo);
     };
     // Densities (with the pull-time sink reset) of logical plane zq: psi of
     // the halo node from wr and of the tile node from v (decoded, reset in
@@ -712,30 +753,37 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     auto dens = [&](int zq, const RawNode<St>& wr, NodeVals<A>& v) {
         const int zp = psi_plane(zq, I.nz, I.wall_z);
         A(*ps)[FP] = psiS[(zq - z0 + 1) & 3];
+        const uint32_t fi = tinfo[2][t];
         double fl = 0.0;
         if (ring) {
             NodeVals<A> h;
             decode_raw<St>(wr, h);
             node_density<A>(I, h);
-            if (in_zrange_sink(zr_ring, zp)) sink_reset<A>(I, h);
-            ps[0][fh] = psi_of<A>(h.rho[0], I.psi_exp);
-            ps[1][fh] = psi_of<A>(h.rho[1], I.psi_exp);
+            if (in_zrange_sink(tinfo[6][t], zp)) sink_reset<A>(I, h);
+            ps[0][hi(fi)] = psi_of<A>(h.rho[0], I.psi_exp);
+            ps[1][hi(fi)] = psi_of<A>(h.rho[1], I.psi_exp);
         }
+        node_density<A>(I, v);
+        if (own && in_zrange_sink(tinfo[4][t], zp)) fl = sink_reset<A>(I, v);
         if (own) {
-            node_density<A>(I, v);
-            if (in_zrange_sink(zr_own, zp)) fl = sink_reset<A>(I, v);
-            ps[0][fo] = psi_of<A>(v.rho[0], I.psi_exp);
-            ps[1][fo] = psi_of<A>(v.rho[1], I.psi_exp);
+            ps[0][lo(fi)] = psi_of<A>(v.rho[0], I.psi_exp);
+            ps[1][lo(fi)] = psi_of<A>(v.rho[1], I.psi_exp);
         }
         if (book && zq >= z0 && zq < z1 && __builtin_amdgcn_ballot_w64(fl != 0.0))
             ewave = wave_uniform(ewave + block_sum_wave(fl));
     };
     auto collide = [&](int z, NodeVals<A>& v) {
         if (!own) return;
-        const uint32_t xy = (uint32_t)y * (uint32_t)I.nx + (uint32_t)x;
-        if (!in_zrange_sink(zr_cur, z)) {
+        const uint32_t o = tinfo[0][t];
+        const uint32_t xy = (uint32_t)hi(o) * (uint32_t)I.nx + (uint32_t)lo(o);
+        if (!in_zrange_sink(tinfo[5][t], z)) {
+            const uint32_t txy = tinfo[3][t];
+            const int fo = lo(tinfo[2][t]);
+            int sc[3], sr[3];
+            pipe_stencil(lo(txy), tw, xper, sc);
+            pipe_stencil(hi(txy), th, yper, sr);
             A S[2][3];
-            force_sum<A, FP>(psiS[(z - z0) & 3], psiS[(z - z0 + 1) & 3], psiS[(z - z0 + 2) & 3], cI, rI, row, S);
+            force_sum<A, FP>(psiS[(z - z0) & 3], psiS[(z - z0 + 1) & 3], psiS[(z - z0 + 2) & 3], sc, sr, row, S);
             collide_node<A>(I, v, S, psiS[(z - z0 + 1) & 3][0][fo], psiS[(z - z0 + 1) & 3][1][fo]);
         }
         store_node<St>(d, I, z, xy, v);
@@ -757,37 +805,39 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             dens(z0, rr2, p0);
         }
         dens(z0 + 1, rr, p1);
-        if (z0 + 2 <= z1) {
-            issue_ring(z0 + 2, rr);
-            issue_own(z0 + 2, p2.f);
-        }
+        issue_ring(z0 + 2, rr);
+        issue_own(z0 + 2, p2.f);
         // Plane z collides from a; plane z+2 (loaded into c) is reduced to
-        // densities; plane z+3 loads into a.
+        // densities (past the halo plane: zeros into a psi slot nothing
+        // reads); plane z+3 loads into a.
         auto step = [&](int z, NodeVals<A>& a, NodeVals<A>& c) {
             __syncthreads();
             collide(z, a);
-            if (z + 2 <= z1) {
-                dens(z + 2, rr, c);
-                if (z + 3 <= z1) {
-                    issue_ring(z + 3, rr);
-                    issue_own(z + 3, a.f);
-                }
-            }
+            dens(z + 2, rr, c);
+            // Keep the next loads after the work that frees their registers:
+            // hoisted, they would hold a fourth population set.
+            __builtin_amdgcn_sched_barrier(0);
+            issue_ring(z + 3, rr);
+            issue_own(z + 3, a.f);
         };
-        for (int z = z0; z < z1; z += 3) {
+        for (int z = z0;; z += 3) {
             step(z, p0, p2);
-            if (z + 1 < z1) step(z + 1, p1, p0);
-            if (z + 2 < z1) step(z + 2, p2, p1);
+            if (z + 1 >= z1) break;
+            step(z + 1, p1, p0);
+            if (z + 2 >= z1) break;
+            step(z + 2, p2, p1);
+            if (z + 3 >= z1) break;
         }
     } else {
         RawNode<St> ro, rr;
         NodeVals<A> va, vb;
         auto issue_into = [&](int zq, RawNode<St>& wo, RawNode<St>& wr) {
             issue_ring(zq, wr);
-            if (own) pull_raw<St>(s, I, x, y, psi_plane(zq, I.nz, I.wall_z), wo);
+            const uint32_t o = tinfo[0][t];
+            if (zq <= z1) pull_raw<St>(s, I, lo(o), hi(o), psi_plane(zq, I.nz, I.wall_z), wo);
         };
         auto dens_from = [&](int zq, NodeVals<A>& keep, const RawNode<St>& wo, const RawNode<St>& wr) {
-            if (own) decode_raw<St>(wo, keep);
+            decode_raw<St>(wo, keep);
             dens(zq, wr, keep);
         };
         // Prologue: two planes in flight at a time (the second pair of raw
@@ -799,24 +849,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             dens_from(z0 - 1, va, ro2, rr2);
             issue_into(z0 + 1, ro2, rr2);
             dens_from(z0, va, ro, rr);
-            if (z0 + 2 <= z1) issue_into(z0 + 2, ro, rr);
+            issue_into(z0 + 2, ro, rr);
             dens_from(z0 + 1, vb, ro2, rr2);
         }
-        for (int z = z0; z < z1; z += 2) {
+        for (int z = z0;; z += 2) {
             __syncthreads();
             collide(z, va);
-            if (z + 2 <= z1) {
-                dens_from(z + 2, va, ro, rr);
-                if (z + 3 <= z1) issue_into(z + 3, ro, rr);
-            }
-            if (z + 1 < z1) {
-                __syncthreads();
-                collide(z + 1, vb);
-                if (z + 3 <= z1) {
-                    dens_from(z + 3, vb, ro, rr);
-                    if (z + 4 <= z1) issue_into(z + 4, ro, rr);
-                }
-            }
+            dens_from(z + 2, va, ro, rr);
+            __builtin_amdgcn_sched_barrier(0);
+            issue_into(z + 3, ro, rr);
+            if (z + 1 >= z1) break;
+            __syncthreads();
+            collide(z + 1, vb);
+            dens_from(z + 3, vb, ro, rr);
+            __builtin_amdgcn_sched_barrier(0);
+            issue_into(z + 4, ro, rr);
+            if (z + 2 >= z1) break;
         }
     }
 

@@ -119,6 +119,10 @@ struct Inst {
     double tau[2];
     double omega[2];       // 1 / tau
     double g;
+    // FP32 copies for the FP32-arithmetic kernels, formed on the host in
+    // FP32 exactly as the kernels would (they stay in scalar registers):
+    float shift_f[2], omega_f[2];
+    float ntg_f[2];        // -tau^c * g, one FP32 product
     double shift[2];       // rho0^c of shifted storage (0 for plain FP64)
     double phi_in, phi_out;
     Sink reset;            // sink that formed the stored state (applied on pull)

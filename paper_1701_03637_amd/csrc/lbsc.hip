@@ -440,6 +440,12 @@ lbsc_status lbsc_create(int32_t n_inst, const lbsc_params* params, lbsc_ctx** ou
         I.shift[0] = c->precision == LBSC_FP64 ? 0.0 : p.shift[0];
         I.shift[1] = c->precision == LBSC_FP64 ? 0.0 : p.shift[1];
         I.phi_in = p.phi_delta[0]; I.phi_out = p.phi_delta[1];
+        for (int cc = 0; cc < 2; ++cc) {
+            I.shift_f[cc] = (float)I.shift[cc];
+            I.omega_f[cc] = (float)I.omega[cc];
+            const float tf = (float)I.tau[cc], gf = (float)I.g;
+            I.ntg_f[cc] = -tf * gf;
+        }
         I.reset = make_sink(p.sink, p.rho_h, p.sink_radius, p.center);
         I.cur = I.reset;
         c->inst.push_back(I);
