@@ -723,7 +723,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     auto lo = [](uint32_t v) { return (int)(v & 0xffffu); };
     auto hi = [](uint32_t v) { return (int)(v >> 16); };
 
-    const int z0 = it.z0, z1 = it.z0 + it.nzc;
+    // The march runs over indices m in [z0, z1) = [0, nzc), plane zs + dz m:
+    // upwards from the chunk's bottom, or downwards from its top. Adjacent
+    // chunks march in opposite directions, so both reach their shared
+    // boundary planes at the same time (both at the start or both at the
+    // end) and the second read of each is served by the cache.
+    const int dz = it.down ? -1 : 1;
+    const int zs = it.down ? it.z0 + it.nzc - 1 : it.z0;
+    const int z0 = 0, z1 = it.nzc;
     const bool book = I.count_reset != 0 && I.reset.kind != kSinkNone;
     // Evaporated mass of this wave: each plane's sink fluxes are summed over
     // the wave (fixed tree order) into one wave-uniform double, so no
@@ -740,18 +747,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     // lanes fetch anyway).
     auto issue_ring = [&](int zq, RawNode<St>& wr) {
         const uint32_t h = tinfo[1][t];
-        if (zq <= z1 && ring) pull_raw<St>(s, I, lo(h), hi(h), psi_plane(zq, I.nz, I.wall_z), wr);
+        if (zq <= z1 && ring) pull_raw<St>(s, I, lo(h), hi(h), psi_plane(zs + dz * zq, I.nz, I.wall_z), wr);
     };
     auto issue_own = [&](int zq, T (&wo)[2][kQ]) {
         const uint32_t o = tinfo[0][t];
-        if (zq <= z1) pull_vals<St>(s, I, lo(o), hi(o), psi_plane(zq, I.nz, I.wall_z), wo);
+        if (zq <= z1) pull_vals<St>(s, I, lo(o), hi(o), psi_plane(zs + dz * zq, I.nz, I.wall_z), wo);
     };
     // Densities (with the pull-time sink reset) of logical plane zq: psi of
     // the halo node from wr and of the tile node from v (decoded, reset in
     // place) into the plane's LDS slot; the flux of reset tile nodes is
     // booked.
     auto dens = [&](int zq, const RawNode<St>& wr, NodeVals<A>& v) {
-        const int zp = psi_plane(zq, I.nz, I.wall_z);
+        const int zp = psi_plane(zs + dz * zq, I.nz, I.wall_z);
         A(*ps)[FP] = psiS[(zq - z0 + 1) & 3];
         const uint32_t fi = tinfo[2][t];
         double fl = 0.0;
@@ -772,8 +779,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         if (book && zq >= z0 && zq < z1 && __builtin_amdgcn_ballot_w64(fl != 0.0))
             ewave = wave_uniform(ewave + block_sum_wave(fl));
     };
-    auto collide = [&](int z, NodeVals<A>& v) {
+    auto collide = [&](int m, NodeVals<A>& v) {
         if (!own) return;
+        const int z = zs + dz * m;
         const uint32_t o = tinfo[0][t];
         const uint32_t xy = (uint32_t)hi(o) * (uint32_t)I.nx + (uint32_t)lo(o);
         if (!in_zrange_sink(tinfo[5][t], z)) {
@@ -782,9 +790,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             int sc[3], sr[3];
             pipe_stencil(lo(txy), tw, xper, sc);
             pipe_stencil(hi(txy), th, yper, sr);
+            // psi slots of march indices m-1, m, m+1; planes z-1 / z+1 swap
+            // roles on a downward march
+            const int sb = m & 3, sc0 = (m + 1) & 3, sa = (m + 2) & 3;
             A S[2][3];
-            force_sum<A, FP>(psiS[(z - z0) & 3], psiS[(z - z0 + 1) & 3], psiS[(z - z0 + 2) & 3], sc, sr, row, S);
-            collide_node<A>(I, v, S, psiS[(z - z0 + 1) & 3][0][fo], psiS[(z - z0 + 1) & 3][1][fo]);
+            force_sum<A, FP>(psiS[dz > 0 ? sb : sa], psiS[sc0], psiS[dz > 0 ? sa : sb], sc, sr, row, S);
+            collide_node<A>(I, v, S, psiS[sc0][0][fo], psiS[sc0][1][fo]);
         }
         store_node<St>(d, I, z, xy, v);
     };
@@ -834,7 +845,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         auto issue_into = [&](int zq, RawNode<St>& wo, RawNode<St>& wr) {
             issue_ring(zq, wr);
             const uint32_t o = tinfo[0][t];
-            if (zq <= z1) pull_raw<St>(s, I, lo(o), hi(o), psi_plane(zq, I.nz, I.wall_z), wo);
+            if (zq <= z1) pull_raw<St>(s, I, lo(o), hi(o), psi_plane(zs + dz * zq, I.nz, I.wall_z), wo);
         };
         auto dens_from = [&](int zq, NodeVals<A>& keep, const RawNode<St>& wo, const RawNode<St>& wr) {
             decode_raw<St>(wo, keep);

@@ -138,12 +138,13 @@ LBSC_HD int64_t eidx(const Inst& I, int c, int i, int z, int64_t xy)
 }
 
 // One block's work: an xy tile [x0, x0+tw) x [y0, y0+th) marched over z in
-// [z0, z0+nzc).
+// [z0, z0+nzc), upwards, or downwards when down != 0 (pipelined step only).
 struct Item {
     int32_t inst;
     int16_t x0, y0;
     int16_t tw, th;
     int16_t z0, nzc;
+    int16_t down, pad;
 };
 
 LBSC_HD int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }

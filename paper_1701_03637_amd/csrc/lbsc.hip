@@ -191,9 +191,17 @@ void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int64_
         chunks = std::min(chunks, std::max(1, I.nz / 16));
         zb = split_range(I.nz, 0, chunks);
     }
-    for (size_t kz = 0; kz + 1 < zb.size(); ++kz)
-        for (size_t ky = 0; ky + 1 < yb.size(); ++ky)
-            for (size_t kx = 0; kx + 1 < xb.size(); ++kx) {
+    // Order: groups of about cols/8 neighbouring tiles, each with all its z
+    // chunks, so that one XCD (a contiguous run of items) holds the chunks
+    // above and below each other; odd chunks march downwards (the pipelined
+    // step reads each shared boundary plane from both sides at the same
+    // time).
+    const int nxt = (int)xb.size() - 1, nch = (int)zb.size() - 1;
+    const int gsz = std::max(1, cols / 8);
+    for (int g0 = 0; g0 < cols; g0 += gsz)
+        for (int kz = 0; kz < nch; ++kz)
+            for (int cix = g0; cix < std::min(g0 + gsz, cols); ++cix) {
+                const int ky = cix / nxt, kx = cix % nxt;
                 Item it{};
                 it.inst = inst;
                 it.x0 = (int16_t)xb[kx];
@@ -202,6 +210,7 @@ void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int64_
                 it.th = (int16_t)(yb[ky + 1] - yb[ky]);
                 it.z0 = (int16_t)zb[kz];
                 it.nzc = (int16_t)(zb[kz + 1] - zb[kz]);
+                it.down = (int16_t)(kz & 1);
                 out.push_back(it);
             }
 }
@@ -244,6 +253,8 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
     if (t.variant == 3 && !pipe_fits)
         return fail(c, LBSC_E_ARG, "tiles.variant 3: a tile has more halo nodes than the %d threads", nt);
     variant = t.variant > 0 ? t.variant : (pipe_fits ? 3 : 1);
+    if (variant != 3)
+        for (auto& it : items) it.down = 0;  // the register-keeping steps march upwards only
     return LBSC_OK;
 }
 
