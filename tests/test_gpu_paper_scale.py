@@ -1,0 +1,79 @@
+"""The paper's evaporating droplet at its own scale (Sec. III C): 256^3 lattice,
+R0 = 65, spherical evaporation boundary R_H = 127, rho_H = 0.02, paper fluid
+(psi = 1 - exp(-rho), g = 3.6, tau = 1), FP32-shifted storage.
+
+R(t) is compared, while the diameter exceeds 20 (the paper's cut-off), with
+RK4 solutions of the sign-fixed plain law (Eq. (mass-dfsum-sim)) and of the
+law with Laplace pressure (Eq. (drop-r-df4)), gamma from the Laplace test of
+test_gpu_physics. About 5e5 steps of a 16.8 M-node lattice: opt-in
+(LBSC_PAPER_SCALE=1), several GPU-minutes.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import lbinputs as li
+from oracle import analytic as an
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow,
+              pytest.mark.skipif(os.environ.get("LBSC_PAPER_SCALE") != "1",
+                                 reason="paper-scale run is opt-in (LBSC_PAPER_SCALE=1)")]
+
+GAMMA = 0.0483   # surface tension of the paper fluid, Laplace test on 64^3 (FP32S)
+
+
+def test_paper_scale_droplet_radius_laws():
+    import paper_1701_03637_amd as lb
+    lb.load_library()
+    n, R0, RH, rho_h = 256, 65.0, 127.0, 0.02
+    p = lb.make_params(n, n, n, g=3.6, psi="exp", precision="fp32s", shift=(0.036, 0.708), sink="none",
+                       rho_h=rho_h, sink_radius=RH, phi_delta=(0.672, -0.672))
+    sim = lb.Sim(p)
+    sim.set_graph(100)
+    a, b = li.droplet(n, n, n, R0, rho_in=0.708, rho_out=0.036)
+    sim.init_from_density(a, b)
+    sim.step(5000)   # interface relaxation without the sink
+    ra = sim.density(0).cpu().numpy()
+    rb = sim.density(1).cpu().numpy()
+    c = n // 2
+    rho_ma0 = float(ra[c - 4:c + 4, c - 4:c + 4, c - 4:c + 4].mean())
+    zz, yy, xx = np.meshgrid(*(np.arange(n, dtype=np.float32) - (n - 1) / 2,) * 3, indexing="ij")
+    r = np.sqrt(xx ** 2 + yy ** 2 + zz ** 2)
+    shell = (r > 100) & (r < 120)
+    rho_mi0 = float(ra[shell].mean())
+    rho_t = float((ra + rb)[shell].mean())
+    del ra, rb, zz, yy, xx, r, shell
+    sim.set_sink("sphere", rho_h, RH)
+    d = sim.diagnostics()
+    ts, rs = [0.0], [d["r_droplet"]]
+    print(f"start: R={rs[0]:.2f} rho_ma={rho_ma0:.4f} rho_mi={rho_mi0:.4f} rho_t={rho_t:.4f}", flush=True)
+    chunk = 10000
+    for k in range(55):
+        sim.step(chunk)
+        d = sim.diagnostics()
+        ts.append(chunk * (k + 1.0))
+        rs.append(d["r_droplet"])
+        print(f"t={ts[-1]:.0f} R={rs[-1]:.3f} E={d['evaporated']:.1f} nonfinite={d['nonfinite']}", flush=True)
+        if rs[-1] < 10.0:
+            break
+    ts, rs = np.array(ts), np.array(rs)
+    ram = 0.5 * (rho_mi0 + rho_h)
+    D = an.diffusion_small_gradient(ram, rho_t - ram, 3.6, "exp")
+    d0 = 2.5
+    t_p, r_p = an.rk4(lambda R: an.droplet_rate_plain(R, RH, d0, D, rho_ma0, rho_mi0, rho_h), rs[0], ts[-1], 500.0)
+    t_l, r_l = an.rk4(lambda R: an.droplet_rate_laplace(R, RH, d0, D, rs[0], GAMMA, rho_ma0, rho_mi0, rho_h),
+                      rs[0], ts[-1], 500.0)
+    plain = np.interp(ts, t_p, r_p)
+    lap = np.interp(ts, t_l, r_l)
+    big = rs > 10.0
+    err_p = float(np.max(np.abs(rs[big] - plain[big])))
+    err_l = float(np.max(np.abs(rs[big] - lap[big])))
+    print(f"R:       {np.round(rs[::5], 2)}\nplain:   {np.round(plain[::5], 2)}\nlaplace: {np.round(lap[::5], 2)}")
+    print(f"max |R - law| while D > 20: plain {err_p:.2f}, Laplace {err_l:.2f} (D={D:.4f}, gamma={GAMMA})")
+    assert np.all(np.diff(rs) < 0), "the droplet must shrink monotonically"
+    assert rs[-1] < 0.5 * rs[0]
+    # both laws within 10% of the initial radius while the diameter exceeds 20
+    assert err_p < 0.1 * rs[0] and err_l < 0.1 * rs[0]

@@ -166,6 +166,7 @@ PIPE_CASES = [
     ((150, 7, 9), False, "faces", (512, 150, 3, 4, 3)),
     ((150, 7, 9), False, "faces", (512, 0, 0, 0, 3)),
     ((200, 5, 11), True, "zmax", (512, 200, 2, 0, 3)),
+    ((40, 24, 21), False, "sphere", (256, 40, 6, 4, 3), (0.8, 1.3)),
 ]
 
 
@@ -173,14 +174,16 @@ PIPE_CASES = [
 @pytest.mark.parametrize("precision", ["fp32s", "fp16s"])
 def test_pipelined_variant_bitwise_identical(lb, case, precision):
     """The pipelined step (one plane of loads ahead, four psi slots, halo
-    wrapped inside tiles that span x or y) gives the same bits as the
-    register-keeping step, and books the same evaporated mass."""
-    (nx, ny, nz), wall, sink, tiles = case
+    wrapped inside tiles that span x or y, chunks marching up and down)
+    gives the same bits as the register-keeping step, and books the same
+    evaporated mass; one case has tau^A != tau^B and a spherical sink."""
+    (nx, ny, nz), wall, sink, tiles = case[:4]
+    tau = case[4] if len(case) > 4 else (1.0, 1.0)
     f0 = li.random_populations(nx, ny, nz, seed=5, base_a=0.3, base_b=0.4, amp=0.05)
 
     def run(t):
         sim = lb.Sim(lb.make_params(nx, ny, nz, wall_z=wall, psi="exp", g=2.0, sink=sink, rho_h=0.03,
-                                    precision=precision))
+                                    sink_radius=0.4 * nz, tau=tau, precision=precision))
         sim.set_tiles(*t)
         sim.init_from_populations(f0)
         sim.step(7)
