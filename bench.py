@@ -38,6 +38,15 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def step_kernel_name(tiles) -> str:
+    """Name of the FP32S step kernel a resolved schedule (nt, tw, th, nzc,
+    variant) launches."""
+    nt, variant = tiles[0], tiles[4]
+    if variant == 3:
+        return f"lbsc::k_step_pipe<lbsc::StF32S, {nt}>"
+    return f"lbsc::k_step<lbsc::StF32S, {nt}, {'false' if variant == 2 else 'true'}>"
+
+
 def measured_traffic(workload: str, precision: str):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
     was taken on the current kernel sources; else None."""
@@ -297,7 +306,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic,
-                     "kernel": "lbsc::k_step<float,...>", "alg_bytes_per_launch": w.nodes * BYTES_PER_LU["fp32s"],
+                     "kernel": step_kernel_name(head["tiles"]), "alg_bytes_per_launch": w.nodes * BYTES_PER_LU["fp32s"],
                      "avg_launch_ms": kms},
         "copy_ceiling_GBps": ceiling,
         "headline": head,
