@@ -266,6 +266,35 @@ def test_sinusoid_decays_with_paper_diffusion_coefficient(mean, g, psi, tau):
     assert abs(d_meas / d_paper - 1) < 0.01, (d_meas, d_paper)
 
 
+def test_diffusion_into_bath_follows_ficks_law():
+    """Sec. III A diffusion test: a box filled with the partner component
+    (rho = 0.7, g = 3.6, psi = 1 - exp(-rho)), a wall at one end and an
+    evaporation boundary holding the diffusing component at rho_H = 0.001 at
+    the other; the component invades the box as Fick's second law (Eq.
+    (fick2)) with the coefficient of Eq. (diffu-t-1) predicts. The reference
+    is an explicit finite-difference solution on the same nodes: the
+    boundary node held at rho_H, a zero-flux mirror half a node beyond z = 0
+    (the half-way bounce-back wall), the partner's gradient negligible."""
+    nz, rho_h = 125, 0.001
+    o = Oracle(OracleParams(4, 4, nz, wall_z=True, g=3.6, psi=PSI_EXP, sink=SINK_ZMAX, rho_h=rho_h))
+    o.init_from_density(np.zeros((nz, 4, 4)), np.full((nz, 4, 4), 0.7))
+    D = an.diffusion_small_gradient(0.5 * rho_h, 0.7, 3.6, "exp")
+    T, dt = 8000, 0.05
+    u = np.zeros(nz)
+    u[-1] = rho_h
+    for _ in range(int(T / dt)):
+        lap = np.empty(nz - 1)
+        lap[1:] = u[2:] - 2 * u[1:-1] + u[:-2]
+        lap[0] = u[1] - u[0]
+        u[:-1] += dt * D * lap
+    o.step(T)
+    ra = o.density()[0]
+    assert np.ptp(ra, axis=(1, 2)).max() < 1e-15   # planar
+    err = np.max(np.abs(ra[:, 0, 0] - u)) / rho_h
+    assert err < 0.005, err   # measured 0.14 % of rho_H
+    assert u[nz // 2] > 0.05 * rho_h   # the front has crossed half the box
+
+
 # ---------------------------------------------------------------------------
 # Planar film (Sec. III B): coexistence and the sqrt(t) law.
 # ---------------------------------------------------------------------------
