@@ -175,6 +175,31 @@ def form_batched(lb, torch, steps, warmup, diag_every, tune_steps):
     }
     res["hbm_frac_alg"] = res["alg_GBps"] / HBM_PEAK_GBPS
     sim.close()
+    # The same 64 boxes as 64 plain contexts stepped one after another (one
+    # launch per box and step, default schedules), the alternative batching
+    # replaces.
+    seq = []
+    for w, (a, b) in zip(ws, dens):
+        s1 = lb.Sim(lb.make_params(w.nx, w.ny, w.nz, g=w.g, psi=w.psi, precision="fp32s", sink=w.sink,
+                                   rho_h=w.rho_h))
+        s1.init_from_density(a, b)
+        seq.append(s1)
+    for s1 in seq:
+        s1.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        for s1 in seq:
+            s1.step(1)
+    ev1.record()
+    torch.cuda.synchronize()
+    seq_wall_ms = (time.perf_counter() - t0) * 1e3
+    for s1 in seq:
+        s1.close()
+    res["sequential_mlups"] = nodes * steps / (seq_wall_ms * 1e-3) / 1e6
+    res["sequential_kernel_ms_per_step"] = ev0.elapsed_time(ev1) / steps
+    res["batched_speedup"] = res["mlups"] / res["sequential_mlups"]
     return res
 
 
