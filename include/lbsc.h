@@ -117,13 +117,13 @@ typedef struct lbsc_ctx lbsc_ctx;
  * xy tile tw x th (tw*th <= nt), z chunk of nzc planes, and the
  * kernel variant: 1 keeps a node's pulled populations in registers from its
  * density pass to its collision, 2 pulls the node again for the collision
- * (fewer registers, more blocks per CU), 3 (FP32S / FP16S storage only) also
- * keeps them but issues each plane's loads one plane ahead of use, with one
- * barrier per plane; it needs one thread per halo node of a tile (the halo
- * of a tile spanning the whole x or y extent is the tile itself), so tiles
- * that break this are rejected. Variants give bitwise identical results.
- * Zero or negative fields mean "choose automatically" (variant: 3 where it
- * applies, else 1). */
+ * (fewer registers, more blocks per CU), 3 (FP64 with nt = 256, FP32S,
+ * FP16S) also keeps them but issues each plane's loads one plane ahead of
+ * use, with one barrier per plane; it needs one thread per halo node of a
+ * tile (the halo of a tile spanning the whole x or y extent is the tile
+ * itself), so tiles that break this are rejected. Variants give bitwise
+ * identical populations. Zero or negative fields mean "choose automatically"
+ * (variant: 3 where it applies, else 1). */
 typedef struct lbsc_tiles {
     int32_t nt, tw, th, nzc, variant;
 } lbsc_tiles;

@@ -614,7 +614,7 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
 }
 
 // ---------------------------------------------------------------------------
-// Software-pipelined step (FP32 arithmetic forms).
+// Software-pipelined step (FP64, FP32S and FP16S storage).
 //
 // Same tiles, arithmetic and results as k_step; the schedule differs:
 //  - the loads of plane z+2 (tile node and one halo node per thread) are
@@ -669,8 +669,12 @@ __host__ __device__ inline void pipe_stencil(int a, int w, bool per, int out[3])
     out[2] = per && a == w - 1 ? 1 : a + 2;
 }
 
+// Waves per SIMD the pipelined step is compiled for: two in FP32 arithmetic
+// (<= 256 VGPRs); one in FP64, whose three population sets take ~490.
+template <class St> constexpr int kPipeWaves = std::is_same_v<typename St::A, double> ? 1 : 2;
+
 template <class St, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_step_pipe(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<St>))) void k_step_pipe(
     const Inst* __restrict__ insts, const Item* __restrict__ items, int n_items, const typename St::T* __restrict__ src,
     typename St::T* __restrict__ dst, double* __restrict__ eacc)
 {

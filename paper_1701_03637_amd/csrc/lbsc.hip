@@ -225,8 +225,10 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
     const int target_items = f64 ? 256 : 4096;
     if (nt != 256 && nt != 512) return fail(c, LBSC_E_ARG, "tiles.nt must be 256 or 512");
     if (t.variant > 3) return fail(c, LBSC_E_ARG, "tiles.variant must be 0, 1, 2 or 3");
-    if (t.variant == 3 && (c->precision == LBSC_FP64 || c->precision == LBSC_FP16N))
-        return fail(c, LBSC_E_ARG, "tiles.variant 3 needs FP32S or FP16S storage");
+    if (t.variant == 3 && c->precision == LBSC_FP16N)
+        return fail(c, LBSC_E_ARG, "tiles.variant 3 needs FP64, FP32S or FP16S storage");
+    if (t.variant == 3 && c->precision == LBSC_FP64 && nt != 256)
+        return fail(c, LBSC_E_ARG, "tiles.variant 3 in FP64 runs 256-thread blocks");
     if (t.tw > 512 || t.th > 512) return fail(c, LBSC_E_ARG, "tiles.tw and tiles.th must be <= 512");
     int64_t total = 0;
     for (auto& I : inst) total += I.n;
@@ -240,7 +242,7 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
         return fail(c, LBSC_E_ARG, "schedule needs %zu work items, more than the %zu reserved", items.size(),
                     c->max_items);
     const int foot = nt == 256 ? lbsc::Foot<256>::kMax : lbsc::Foot<512>::kMax;
-    bool pipe_fits = c->precision == LBSC_FP32S || c->precision == LBSC_FP16S;
+    bool pipe_fits = c->precision == LBSC_FP32S || c->precision == LBSC_FP16S || (f64 && nt == 256);
     for (auto& it : items) {
         if (it.tw * it.th > nt || (it.tw + 2) * (it.th + 2) > foot)
             return fail(c, LBSC_E_ARG, "internal: tile %dx%d does not fit %d threads", it.tw, it.th, nt);
@@ -316,9 +318,12 @@ hipError_t launch_pipe_t(lbsc_ctx* c, hipStream_t s, int src)
 template <class St>
 hipError_t launch_step_p(lbsc_ctx* c, hipStream_t s, int src)
 {
-    if constexpr (!std::is_same_v<typename St::A, double> && !St::kNode)
+    if constexpr (std::is_same_v<typename St::A, double>) {
+        if (c->variant == 3) return launch_pipe_t<St, 256>(c, s, src);  // one wave per SIMD: 256 threads only
+    } else if constexpr (!St::kNode) {
         if (c->variant == 3)
             return c->nt == 512 ? launch_pipe_t<St, 512>(c, s, src) : launch_pipe_t<St, 256>(c, s, src);
+    }
     return c->variant == 2 ? launch_step_k<St, false>(c, s, src) : launch_step_k<St, true>(c, s, src);
 }
 
@@ -692,7 +697,8 @@ lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
     for (int variant : {1, 2, 3})
         for (int nt : {256, 512}) {
             if (nt == 512 && c->precision == LBSC_FP64 && variant == 1) continue;  // exceeds the register file
-            if (variant == 3 && c->precision != LBSC_FP32S && c->precision != LBSC_FP16S) continue;
+            if (variant == 3 && (c->precision == LBSC_FP16N || (c->precision == LBSC_FP64 && nt != 256)))
+                continue;
             for (int tw : {0, 32, 64, 128})
                 for (int nzc : {0, 8, 16, 32, 64}) cands.push_back(lbsc_tiles{nt, tw, 0, nzc, variant});
         }

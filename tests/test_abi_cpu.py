@@ -72,7 +72,7 @@ def test_tile_schedule_errors(lib):
     h = ctypes.c_void_p()
     p = lbsc.make_params(32, 32, 32)
     assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == 0
-    for t in (lbsc.Tiles(128, 0, 0, 0, 0), lbsc.Tiles(32, 16, 2, 0, 0), lbsc.Tiles(256, 600, 0, 0, 0), lbsc.Tiles(256, 0, 0, 0, 3)):
+    for t in (lbsc.Tiles(128, 0, 0, 0, 0), lbsc.Tiles(32, 16, 2, 0, 0), lbsc.Tiles(256, 600, 0, 0, 0), lbsc.Tiles(512, 0, 0, 0, 3)):
         assert lib.lbsc_set_tiles(h, ctypes.byref(t)) == -1
     assert lib.lbsc_set_tiles(h, ctypes.byref(lbsc.Tiles(512, 32, 16, 4, 2))) == 0
     nit = ctypes.c_int32()
@@ -84,8 +84,9 @@ def test_tile_schedule_errors(lib):
 
 def test_kernel_variant_resolution(lib):
     """Variant 0 resolves to the pipelined step where every tile's halo has a
-    thread per node and the storage is FP32S / FP16S, else to the
-    register-keeping step; an explicit variant 3 that does not fit fails."""
+    thread per node and the storage is FP32S / FP16S, or FP64 in 256-thread
+    blocks, else to the register-keeping step; an explicit variant 3 that
+    does not fit fails."""
     from paper_1701_03637_amd import lbsc
 
     def resolve(prec, n, tiles):
@@ -100,7 +101,9 @@ def test_kernel_variant_resolution(lib):
 
     assert resolve("fp32s", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 512, 3)
     assert resolve("fp16s", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 512, 3)
-    assert resolve("fp64", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 256, 1)
+    assert resolve("fp64", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 256, 3)
+    assert resolve("fp64", (128, 128, 128), (512, 0, 0, 0, 0)) == (0, 512, 1)
+    assert resolve("fp64", (128, 128, 128), (512, 0, 0, 0, 3))[0] == -1
     assert resolve("fp16n", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 512, 1)
     # 128 x 2 tiles of a 256-wide lattice: 2 (128 + 2) + 2 x 2 = 264 halo nodes
     assert resolve("fp32s", (256, 64, 32), (256, 128, 2, 0, 0)) == (0, 256, 1)

@@ -171,7 +171,7 @@ PIPE_CASES = [
 
 
 @pytest.mark.parametrize("case", PIPE_CASES)
-@pytest.mark.parametrize("precision", ["fp32s", "fp16s"])
+@pytest.mark.parametrize("precision", ["fp32s", "fp16s", "fp64"])
 def test_pipelined_variant_bitwise_identical(lb, case, precision):
     """The pipelined step (one plane of loads ahead, four psi slots, halo
     wrapped inside tiles that span x or y, chunks marching up and down)
@@ -179,6 +179,8 @@ def test_pipelined_variant_bitwise_identical(lb, case, precision):
     evaporated mass; one case has tau^A != tau^B and a spherical sink."""
     (nx, ny, nz), wall, sink, tiles = case[:4]
     tau = case[4] if len(case) > 4 else (1.0, 1.0)
+    if precision == "fp64" and tiles[0] != 256:
+        pytest.skip("the FP64 pipelined step runs 256-thread blocks")
     f0 = li.random_populations(nx, ny, nz, seed=5, base_a=0.3, base_b=0.4, amp=0.05)
 
     def run(t):
@@ -188,7 +190,7 @@ def test_pipelined_variant_bitwise_identical(lb, case, precision):
         sim.init_from_populations(f0)
         sim.step(7)
         return sim
-    ref, sim = run((256, 0, 0, 0, 1)), run(tiles)
+    ref, sim = run((256, 0, 0, 0, 1)), run(tiles if precision != "fp64" or tiles[4] != 0 else (256, *tiles[1:4], 3))
     assert sim.tiles()[4] == 3
     assert torch.equal(sim.populations(), ref.populations())
     e_ref, e = ref.diagnostics()["evaporated"], sim.diagnostics()["evaporated"]
