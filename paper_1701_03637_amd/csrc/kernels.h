@@ -6,6 +6,11 @@
 // Storage. The populations of one instance live in a z-slab-major arena: the
 // populations of one z-plane form a contiguous slab, so a pull needs only the
 // three slab bases z-1, z, z+1 plus one 32-bit in-plane offset per lane.
+// Within a slab, the FP64 and FP16 forms keep population i of both
+// components in one plane of (A, B) pairs: the two values a pull takes from
+// the same source node are adjacent and move with one load or store
+// instruction. FP32S keeps one plane per (component, population): its
+// single-element accesses are already dword-wide, and it measured faster so.
 // The stored buffer holds post-collision populations f*(t-1); the state S(t)
 // of the method (post-stream, post-sink) is obtained by pulling,
 //   f_i(x) = f*_i(x - e_i), or f*_opp(i)(x) across a z-seam wall,
@@ -38,13 +43,15 @@ namespace lbsc {
 
 // Storage policies: element type T of the population planes, arithmetic type
 // A, and whether the rest population carries a per-node shift (kNode).
-struct StF64 { using T = double; using A = double; static constexpr bool kNode = false; };
-struct StF32S { using T = float; using A = float; static constexpr bool kNode = false; };
-struct StF16S { using T = _Float16; using A = float; static constexpr bool kNode = false; };
-struct StF16N { using T = _Float16; using A = float; static constexpr bool kNode = true; };
+// kPair: (A, B) pair planes rather than one plane per component.
+struct StF64 { using T = double; using A = double; static constexpr bool kNode = false, kPair = true; };
+struct StF32S { using T = float; using A = float; static constexpr bool kNode = false, kPair = false; };
+struct StF16S { using T = _Float16; using A = float; static constexpr bool kNode = false, kPair = true; };
+struct StF16N { using T = _Float16; using A = float; static constexpr bool kNode = true, kPair = true; };
 
-// Slab elements (of T) per in-plane element: 38 planes, or for FP16N
-// 36 FP16 planes plus two FP32 rest planes (= 4 FP16 planes).
+// Slab elements (of T) per in-plane element: 2 x 19 values, or for FP16N
+// 18 planes of FP16 pairs plus one plane of FP32 rest pairs (= 4 FP16
+// elements per node).
 template <class S> constexpr int kSlabPlanes = S::kNode ? 40 : 2 * kQ;
 
 // FP16N encoding constants: k_i = w_i / w_0 as FP32 and 1/K with
@@ -61,20 +68,55 @@ constexpr float kInvKLo = (float)(1.0 / kK - (double)kInvK);
 // y / K rounded once (to within a tail rounding): head product plus tail.
 __device__ __forceinline__ float div_k(float y) { return __builtin_fmaf(y, kInvK, y * kInvKLo); }
 
-// Byte offset of population plane (c, i) within a slab of plane stride ps.
-template <class S>
-__host__ __device__ __forceinline__ uint32_t plane_off(int c, int i, uint32_t ps)
+// Narrowing of an arithmetic value to the storage type. An FP32 value bound
+// for FP16 is formed in a register first: otherwise the compiler may fuse
+// the multiply-add that produces it into a mixed-precision FMA that rounds
+// once, straight to FP16, where the source rounds to FP32 and then to FP16.
+// It does so at some inlined copies of a store and not at others, which
+// would make a node's stored bits depend on which copy stored it.
+template <typename T, typename A> __device__ __forceinline__ T narrow(A x)
 {
-    if constexpr (S::kNode)
-        return i == 0 ? (36u * ps * 2u + (uint32_t)c * ps * 4u) : ((uint32_t)(c * 18 + i - 1) * ps * 2u);
-    else
-        return (uint32_t)(c * kQ + i) * ps * (uint32_t)sizeof(typename S::T);
+    if constexpr (sizeof(T) < sizeof(A)) asm("" : "+v"(x));
+    return (T)x;
 }
 
-// Bytes per element of plane i.
+// Bytes per element of population i.
 template <class S> __host__ __device__ constexpr uint32_t elem_bytes(int i)
 {
     return (S::kNode && i == 0) ? 4u : (uint32_t)sizeof(typename S::T);
+}
+
+// Bytes per node of the pair plane of population i (A then B).
+template <class S> __host__ __device__ constexpr uint32_t pair_bytes(int i) { return 2u * elem_bytes<S>(i); }
+
+// Bytes between in-plane neighbours in the plane holding element (c, i).
+template <class S> __host__ __device__ constexpr uint32_t node_stride(int i)
+{
+    return S::kPair ? pair_bytes<S>(i) : elem_bytes<S>(i);
+}
+
+// Byte offset of the pair plane of population i within a slab of plane
+// stride ps; FP16N puts the FP32 rest pairs after the 18 FP16 pair planes.
+template <class S>
+__host__ __device__ __forceinline__ uint32_t pair_off(int i, uint32_t ps)
+{
+    static_assert(S::kPair, "pair planes only");
+    if constexpr (S::kNode)
+        return i == 0 ? 18u * ps * 4u : (uint32_t)(i - 1) * ps * 4u;
+    else
+        return (uint32_t)i * ps * pair_bytes<S>(i);
+}
+
+// Byte offset of element (c, i) of in-plane node 0; node xy adds
+// xy * node_stride(i).
+template <class S>
+__host__ __device__ __forceinline__ uint32_t plane_off(int c, int i, uint32_t ps)
+{
+    static_assert(S::kPair || !S::kNode, "per-node encodings use pair planes");
+    if constexpr (S::kPair)
+        return pair_off<S>(i, ps) + (uint32_t)c * elem_bytes<S>(i);
+    else
+        return (uint32_t)(c * kQ + i) * ps * elem_bytes<S>(i);
 }
 
 template <typename A> __device__ __forceinline__ A psi_of(A rho, int psi_exp);
@@ -160,6 +202,53 @@ __device__ __forceinline__ void bstore(_Float16 v, Rsrc r, uint32_t voff, uint32
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)voff, (int)soff, kStorePolicy);
 }
 
+// One (A, B) pair of adjacent elements in one instruction.
+template <typename T> struct Pair {
+    T a, b;
+};
+using U2 = unsigned int __attribute__((ext_vector_type(2)));
+using U4 = unsigned int __attribute__((ext_vector_type(4)));
+using H2 = _Float16 __attribute__((ext_vector_type(2)));
+using F2 = float __attribute__((ext_vector_type(2)));
+using D2 = double __attribute__((ext_vector_type(2)));
+
+template <typename T> __device__ __forceinline__ Pair<T> bload2(Rsrc r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ Pair<float> bload2<float>(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    const F2 v = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+    return {v.x, v.y};
+}
+template <> __device__ __forceinline__ Pair<double> bload2<double>(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    const D2 v = __builtin_bit_cast(D2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+    return {v.x, v.y};
+}
+template <> __device__ __forceinline__ Pair<_Float16> bload2<_Float16>(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    const H2 v = __builtin_bit_cast(H2, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+    return {v.x, v.y};
+}
+
+__device__ __forceinline__ void bstore2(float a, float b, Rsrc r, uint32_t voff, uint32_t soff)
+{
+    // Register operands: built straight from an array element, the pair is
+    // widened into a two-element load from the array, which then can no
+    // longer live in registers.
+    asm("" : "+v"(a), "+v"(b));
+    const F2 v = {a, b};
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, (int)voff, (int)soff, kStorePolicy);
+}
+__device__ __forceinline__ void bstore2(double a, double b, Rsrc r, uint32_t voff, uint32_t soff)
+{
+    const D2 v = {a, b};
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, v), r, (int)voff, (int)soff, kStorePolicy);
+}
+__device__ __forceinline__ void bstore2(_Float16 a, _Float16 b, Rsrc r, uint32_t voff, uint32_t soff)
+{
+    const H2 v = {a, b};
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)voff, (int)soff, kStorePolicy);
+}
+
 // Raw stored values of one pulled node, as loaded: the loads can be issued
 // well before the values are decoded. FP16N carries, per population, the
 // moving value h_i and the FP32 rest deviation d_0 of its source node.
@@ -220,10 +309,17 @@ __device__ __forceinline__ void pull_vals(const typename S::T* __restrict__ src,
     static_assert(!S::kNode, "per-node encodings load through RawNode");
     const PullAddr<S> a(src, I, x, y, z);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i)
+    for (int i = 0; i < kQ; ++i) {
+        if constexpr (S::kPair) {
+            const Pair<T> p = bload2<T>(a.rsrc(i), a.xy(i) * pair_bytes<S>(i), pair_off<S>(a.q(i), a.ps));
+            v[0][i] = p.a;
+            v[1][i] = p.b;
+        } else {
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
-            v[c][i] = bload<T>(a.rsrc(i), a.xy(i) * (uint32_t)sizeof(T), plane_off<S>(c, a.q(i), a.ps));
+            for (int c = 0; c < 2; ++c)
+                v[c][i] = bload<T>(a.rsrc(i), a.xy(i) * (uint32_t)sizeof(T), plane_off<S>(c, a.q(i), a.ps));
+        }
+    }
 }
 
 // Issues the loads of the pull of node (x, y, z) into a raw set.
@@ -235,12 +331,16 @@ __device__ __forceinline__ void pull_raw(const typename S::T* __restrict__ src, 
     if constexpr (S::kNode) {
         const PullAddr<S> a(src, I, x, y, z);
 #pragma unroll
-        for (int i = 0; i < kQ; ++i)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                w.d0[c][i] = bload<float>(a.rsrc(i), a.xy(i) * 4u, plane_off<S>(c, 0, a.ps));
-                if (i != 0) w.h[c][i] = bload<T>(a.rsrc(i), a.xy(i) * 2u, plane_off<S>(c, a.q(i), a.ps));
+        for (int i = 0; i < kQ; ++i) {
+            const Pair<float> d = bload2<float>(a.rsrc(i), a.xy(i) * pair_bytes<S>(0), pair_off<S>(0, a.ps));
+            w.d0[0][i] = d.a;
+            w.d0[1][i] = d.b;
+            if (i != 0) {
+                const Pair<T> h = bload2<T>(a.rsrc(i), a.xy(i) * pair_bytes<S>(i), pair_off<S>(a.q(i), a.ps));
+                w.h[0][i] = h.a;
+                w.h[1][i] = h.b;
             }
+        }
     } else {
         pull_vals<S>(src, I, x, y, z, w.v);
     }
@@ -280,25 +380,33 @@ __device__ __forceinline__ void store_node(typename S::T* __restrict__ dst, cons
     using T = typename S::T;
     const Rsrc dz = slab_rsrc(dst + (int64_t)z * I.slab);
     const uint32_t ps = (uint32_t)I.ps;
+    if constexpr (S::kNode) {
+        // moving deviations relative to k_i d_0 in FP16; the rest deviation
+        // takes their rounding so the decoded node sums to drho (up to FP32
+        // rounding).
+        float hsum[2] = {0.f, 0.f};
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        if constexpr (S::kNode) {
-            // moving deviations relative to k_i d_0 in FP16; the rest
-            // deviation takes their rounding so the decoded node sums to drho
-            // (up to FP32 rounding).
-            const float d0 = v.f[c][0];
-            float hsum = 0.f;
+        for (int i = 1; i < kQ; ++i) {
+            T h[2];
 #pragma unroll
-            for (int i = 1; i < kQ; ++i) {
-                const T h = (T)(v.f[c][i] - kRatio(i) * d0);
-                hsum += (float)h;
-                bstore(h, dz, xy * 2u, plane_off<S>(c, i, ps));
+            for (int c = 0; c < 2; ++c) {
+                h[c] = narrow<T>(v.f[c][i] - kRatio(i) * v.f[c][0]);
+                hsum[c] += (float)h[c];
             }
-            bstore(div_k(v.drho[c] - hsum), dz, xy * 4u, plane_off<S>(c, 0, ps));
-        } else {
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) bstore((T)v.f[c][i], dz, xy * (uint32_t)sizeof(T), plane_off<S>(c, i, ps));
+            bstore2(h[0], h[1], dz, xy * pair_bytes<S>(i), pair_off<S>(i, ps));
         }
+        bstore2(div_k(v.drho[0] - hsum[0]), div_k(v.drho[1] - hsum[1]), dz, xy * pair_bytes<S>(0),
+                pair_off<S>(0, ps));
+    } else if constexpr (S::kPair) {
+#pragma unroll
+        for (int i = 0; i < kQ; ++i)
+            bstore2(narrow<T>(v.f[0][i]), narrow<T>(v.f[1][i]), dz, xy * pair_bytes<S>(i), pair_off<S>(i, ps));
+    } else {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int i = 0; i < kQ; ++i)
+                bstore(narrow<T>(v.f[c][i]), dz, xy * (uint32_t)sizeof(T), plane_off<S>(c, i, ps));
     }
 }
 
@@ -911,11 +1019,11 @@ __device__ __forceinline__ void put_slot(typename S::T* __restrict__ d, const In
     using T = typename S::T;
     using A = typename S::A;
     char* slab = reinterpret_cast<char*>(d + (int64_t)z * I.slab);
-    const uint32_t off = plane_off<S>(c, i, (uint32_t)I.ps) + (uint32_t)xy * elem_bytes<S>(i);
+    const uint32_t off = plane_off<S>(c, i, (uint32_t)I.ps) + (uint32_t)xy * node_stride<S>(i);
     if constexpr (S::kNode) {
         const float d0 = (float)(f0 - wgt(0) * I.shift[c]);
         if (i == 0) *reinterpret_cast<float*>(slab + off) = d0;
-        else *reinterpret_cast<T*>(slab + off) = (T)((float)(val - wgt(i) * I.shift[c]) - kRatio(i) * d0);
+        else *reinterpret_cast<T*>(slab + off) = narrow<T>((float)(val - wgt(i) * I.shift[c]) - kRatio(i) * d0);
     } else {
         *reinterpret_cast<T*>(slab + off) = (T)(A)(val - wgt(i) * I.shift[c]);
     }

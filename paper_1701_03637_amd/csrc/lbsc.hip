@@ -998,17 +998,27 @@ int32_t lbsc_selftest(void)
         for (int h : hits)
             if (h != 1) ++bad;
     }
-    // Plane byte ranges of every storage form are disjoint and fill the slab.
+    // Every byte of a slab holds exactly one element (c, i) of one in-plane
+    // node, and each access is aligned to its width: a pair for the paired
+    // forms (one instruction moves both components), one element otherwise.
     auto check_layout = [&](auto tag) {
         using S = decltype(tag);
-        for (uint32_t ps : {64u, 4160u, 262144u}) {
-            std::vector<std::pair<uint32_t, uint32_t>> r;
+        for (uint32_t ps : {64u, 4160u, 65536u}) {
+            const uint32_t bytes = (uint32_t)kSlabPlanes<S> * ps * (uint32_t)sizeof(typename S::T);
+            std::vector<uint8_t> owner(bytes, 0);
             for (int c = 0; c < 2; ++c)
-                for (int i = 0; i < kQ; ++i) r.push_back({plane_off<S>(c, i, ps), plane_off<S>(c, i, ps) + ps * elem_bytes<S>(i)});
-            std::sort(r.begin(), r.end());
-            for (size_t k = 0; k + 1 < r.size(); ++k)
-                if (r[k].second != r[k + 1].first) ++bad;
-            if (r.front().first != 0 || r.back().second != (uint32_t)kSlabPlanes<S> * ps * (uint32_t)sizeof(typename S::T)) ++bad;
+                for (int i = 0; i < kQ; ++i) {
+                    const uint32_t e = elem_bytes<S>(i), st = node_stride<S>(i);
+                    const uint32_t align = S::kPair ? pair_bytes<S>(i) : e;
+                    for (uint32_t xy = 0; xy < ps; ++xy) {
+                        const uint32_t o = plane_off<S>(c, i, ps) + xy * st;
+                        if (o + e > bytes) { ++bad; continue; }
+                        if ((o - (uint32_t)c * (S::kPair ? e : 0u)) % align) ++bad;
+                        for (uint32_t b = 0; b < e; ++b) ++owner[o + b];
+                    }
+                }
+            for (uint8_t k : owner)
+                if (k != 1) ++bad;
         }
     };
     check_layout(StF64{});
