@@ -247,7 +247,7 @@ def main():
     ap.add_argument("--tiles", default="",
                     help="pin the headline schedule as nt,tw,th,nzc,variant (skips its tuner)")
     ap.add_argument("--tune-steps", type=int, default=20, help="steps per candidate of the tile tuner (0: defaults)")
-    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--cpu-steps", type=int, default=120)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -154,22 +154,23 @@ std::vector<int> split_range(int n, int w, int parts)
     return b;
 }
 
-void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int64_t total_nodes, int target_items,
-                    std::vector<Item>& out)
+void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int min_rows, int64_t total_nodes,
+                    int target_items, std::vector<Item>& out)
 {
     // Defaults from tile sweeps on MI355X: a tile spans the whole x extent
-    // while its two halo rows fit the block (nx <= nt / 2: contiguous reads,
-    // no x halo), else x splits evenly into parts of at most 128; as many
-    // rows as the block holds, split evenly so that no block runs a thin
-    // ragged tile; about target_items blocks per context with at least 16
-    // planes per z chunk (each chunk re-derives the densities of two extra
-    // planes). Explicit tw / th / nzc give fixed sizes with a ragged last
-    // tile.
-    const int cap = std::min(128, nt);
+    // (contiguous reads, no x halo) while the block still holds min_rows rows
+    // of it, else x splits evenly into parts of at most 128 (and at most
+    // nt / min_rows); as many rows as the block holds, split evenly so that
+    // no block runs a thin ragged tile; about target_items blocks per context
+    // with at least 16 planes per z chunk (each chunk re-derives the
+    // densities of two extra planes). Explicit tw / th / nzc give fixed sizes
+    // with a ragged last tile.
+    const int full = std::max(1, nt / min_rows);
+    const int cap = std::min(128, full);
     std::vector<int> xb, yb, zb;
     if (t.tw > 0) {
         xb = split_range(I.nx, std::min({t.tw, I.nx, nt}), 0);
-    } else if (I.nx <= nt / 2) {
+    } else if (I.nx <= full) {
         xb = split_range(I.nx, 0, 1);
     } else {
         xb = split_range(I.nx, 0, (I.nx + cap - 1) / cap);
@@ -230,19 +231,27 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
     if (t.variant == 3 && c->precision == LBSC_FP64 && nt != 256)
         return fail(c, LBSC_E_ARG, "tiles.variant 3 in FP64 runs 256-thread blocks");
     if (t.tw > 512 || t.th > 512) return fail(c, LBSC_E_ARG, "tiles.tw and tiles.th must be <= 512");
+    // Minimum rows of a default tile. A halo row streams like the tile; a
+    // halo column node touches its own cache line per population, so full
+    // width stays cheaper down to 3 rows for the pipelined step (2-row tiles
+    // pulled twice their nodes and lost to 64 x 4 in FP64). The
+    // register-keeping steps pay more per halo pull and run best on 8 rows.
+    const bool pipe_ok = c->precision == LBSC_FP32S || c->precision == LBSC_FP16S || (f64 && nt == 256);
+    const int want = t.variant > 0 ? t.variant : (pipe_ok ? 3 : 1);
+    const int min_rows = want == 3 ? 3 : 8;
     int64_t total = 0;
     for (auto& I : inst) total += I.n;
     items.clear();
     for (int k = 0; k < (int)inst.size(); ++k) {
         inst[k].item_begin = (int32_t)items.size();
-        instance_items(inst[k], k, t, nt, total, target_items, items);
+        instance_items(inst[k], k, t, nt, min_rows, total, target_items, items);
         inst[k].item_end = (int32_t)items.size();
     }
     if (items.size() > c->max_items)
         return fail(c, LBSC_E_ARG, "schedule needs %zu work items, more than the %zu reserved", items.size(),
                     c->max_items);
     const int foot = nt == 256 ? lbsc::Foot<256>::kMax : lbsc::Foot<512>::kMax;
-    bool pipe_fits = c->precision == LBSC_FP32S || c->precision == LBSC_FP16S || (f64 && nt == 256);
+    bool pipe_fits = pipe_ok;
     for (auto& it : items) {
         if (it.tw * it.th > nt || (it.tw + 2) * (it.th + 2) > foot)
             return fail(c, LBSC_E_ARG, "internal: tile %dx%d does not fit %d threads", it.tw, it.th, nt);
@@ -708,8 +717,21 @@ lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
     const lbsc_tiles before = c->tiles;
     const int graph_before = c->graph_steps;
     c->graph_steps = 0;
-    float best = 1e30f;
-    lbsc_tiles best_t = before;
+    // Time of `n` steps of schedule t after a 2-step warm-up; negative if
+    // the schedule does not apply.
+    auto time_schedule = [&](const lbsc_tiles& t, int n, float& ms) -> lbsc_status {
+        ms = -1.f;
+        if (apply_schedule(c, t) != LBSC_OK) return LBSC_OK;
+        lbsc_status st = lbsc_step(c, 2);
+        if (st) return st;
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        if ((st = lbsc_step(c, n))) return st;
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        return LBSC_OK;
+    };
+    std::vector<std::pair<float, lbsc_tiles>> timed;
     std::vector<std::string> seen;
     for (const auto& t : cands) {
         if (apply_schedule(c, t) != LBSC_OK) continue;
@@ -718,16 +740,24 @@ lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
         key += std::to_string(c->nt) + "v" + std::to_string(c->variant);
         if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
         seen.push_back(key);
-        if ((s = lbsc_step(c, 2))) break;  // warm-up
-        HIPCHK(c, hipEventRecord(e0, c->stream));
-        if ((s = lbsc_step(c, steps))) break;
-        HIPCHK(c, hipEventRecord(e1, c->stream));
-        HIPCHK(c, hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-            best = ms;
-            best_t = t;
+        float ms;
+        if ((s = time_schedule(t, steps, ms))) break;
+        if (ms >= 0.f) timed.push_back({ms, t});
+    }
+    // The three fastest again over three times the steps: a single short
+    // run can misorder schedules a few percent apart.
+    float best = 1e30f;
+    lbsc_tiles best_t = before;
+    if (!s) {
+        std::stable_sort(timed.begin(), timed.end(),
+                         [](const auto& a, const auto& b) { return a.first < b.first; });
+        for (size_t k = 0; k < std::min<size_t>(3, timed.size()); ++k) {
+            float ms;
+            if ((s = time_schedule(timed[k].second, 3 * steps, ms))) break;
+            if (ms >= 0.f && ms < best) {
+                best = ms;
+                best_t = timed[k].second;
+            }
         }
     }
     (void)hipEventDestroy(e0);
@@ -1068,12 +1098,13 @@ int32_t lbsc_selftest(void)
         for (int nt : {256, 512})
             for (int tw : {0, 8, 16, 32, 64, 128, 200, 256})
                 for (int nzc : {0, 4, 16})
-                for (int target : {256, 4096}) {
+                for (int target : {256, 4096})
+                for (int min_rows : {3, 8}) {
                     Inst I{};
                     I.nx = d[0]; I.ny = d[1]; I.nz = d[2];
                     I.n = (int64_t)d[0] * d[1] * d[2];
                     std::vector<Item> items;
-                    instance_items(I, 0, lbsc_tiles{nt, tw, 0, nzc, 0}, nt, I.n, target, items);
+                    instance_items(I, 0, lbsc_tiles{nt, tw, 0, nzc, 0}, nt, min_rows, I.n, target, items);
                     std::vector<unsigned char> cover((size_t)I.n, 0);
                     for (auto& it : items) {
                         if (it.tw * it.th > nt) ++bad;

@@ -115,10 +115,12 @@ def test_kernel_variant_resolution(lib):
 
 
 def test_default_tiles_split_evenly(lib):
-    """Automatic schedules split x, y and z into near-equal parts: a 156^3
-    box gets full-width tiles of 3 rows (52 tiles; 156 = 3 x 52) in 9 chunks,
-    a 300-wide box three 100-wide tiles of 5 rows; the 128^3 droplet gets 32
-    tiles of 128 x 4 in 8 chunks of 16 planes."""
+    """Automatic schedules split x, y and z into near-equal parts, with tiles
+    of at least 3 rows for the pipelined step and 8 for the register-keeping
+    one: a 156^3 box gets full-width tiles of 3 rows (52 tiles; 156 = 3 x 52)
+    in 9 chunks, a 300-wide box three 100-wide tiles of 5 rows; the 128^3
+    droplet gets 32 tiles of 128 x 4 in 8 chunks of 16 planes (FP64, 256
+    threads: 64 tiles of 64 x 4 in 4 chunks)."""
     from paper_1701_03637_amd import lbsc
 
     def items(n, prec):
@@ -134,3 +136,7 @@ def test_default_tiles_split_evenly(lib):
     assert items((300, 40, 32), "fp32s") == 3 * 8 * 2
     assert items((128, 128, 128), "fp32s") == 32 * 8
     assert items((128, 128, 128), "fp64") == 64 * 4
+    # cases where full-width tiles would be too thin
+    assert items((200, 9, 16), "fp32s") == 2 * 2     # 100 x 5 (full width: 2 rows, 5 tiles)
+    assert items((100, 9, 16), "fp64") == 2 * 2      # 50 x 5 (full width: 2 rows, 5 tiles)
+    assert items((100, 11, 16), "fp16n") == 2 * 2    # 50 x 10 (full width: 5 rows, 3 tiles)

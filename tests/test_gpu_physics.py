@@ -3,10 +3,12 @@
 
 - Sec. III B: a 4x4x128 film equilibrated without the sink, then evaporating
   towards rho_H in {0.035, 0.03, 0.02} for 10^6 steps: (x_H - d0 - x_I)^2 is
-  linear in t with slope 2K (sign-fixed Eq. (xt)).
+  linear in t with slope 2K (sign-fixed Eq. (xt)). With rho_H = 0.045 above
+  the minority density the same boundary condenses vapour onto the film
+  (Sec. II C, Sec. IV outlook): K < 0 and the film grows.
 - Sec. III C: surface tension from static droplets (Laplace test), then a small
-  evaporating droplet against RK4 solutions of the sign-fixed Eqs.
-  (mass-dfsum-sim) and (drop-r-df4).
+  evaporating droplet, and a small droplet growing by condensation, against
+  RK4 solutions of the sign-fixed Eqs. (mass-dfsum-sim) and (drop-r-df4).
 """
 import math
 
@@ -51,7 +53,7 @@ def test_film_coexistence_gpu(film_state):
     assert abs(rho_mi - 0.036) < 0.001 and abs(rho_ma - 0.704) < 0.006, (rho_ma, rho_mi)
 
 
-@pytest.mark.parametrize("rho_h", [0.035, 0.03, 0.02])
+@pytest.mark.parametrize("rho_h", [0.035, 0.03, 0.02, 0.045])
 def test_film_sqrt_t_law_paper_length(lb, film_state, rho_h):
     f, ra, rb = film_state
     rho_ma, rho_mi, rho_t = ra[20:44].mean(), ra[84:108].mean(), ra[100] + rb[100]
@@ -68,7 +70,10 @@ def test_film_sqrt_t_law_paper_length(lb, film_state, rho_h):
         ts.append((k + 1) * (T // nrec))
         xs.append(sim.diagnostics()["z_interface"])
     ts, xs = np.array(ts, float), np.array(xs)
-    assert np.all(np.diff(xs) < 0), "film must evaporate"
+    if rho_h < rho_mi:
+        assert np.all(np.diff(xs) < 0), "film must evaporate"
+    else:
+        assert np.all(np.diff(xs) > 0), "film must grow by condensation"
     x_h = 127.0
     y = (x_h - xs) ** 2
     sel = ts > 0.1 * T
@@ -81,8 +86,13 @@ def test_film_sqrt_t_law_paper_length(lb, film_state, rho_h):
     print(f"rho_H={rho_h}: x0={x0:.3f} x_I(1e6)={xs[-1]:.3f} slope/2K={ratio:.4f} R2={r2:.6f}")
     assert r2 > 0.999
     # rho_mi - rho_H is only 0.0011 at rho_H = 0.035, so a 1e-4 uncertainty of
-    # the minority density moves K by ~9%: that case gets a wider band.
-    assert abs(ratio - 1) < (0.15 if rho_h == 0.035 else 0.10)
+    # the minority density moves K by ~9%: that case gets a wider band. The
+    # condensing film's vapour (mean rho_A ~ 0.04) is the furthest from
+    # symmetric composition, where Eq. (diffu-t-1)'s small-gradient D^c
+    # overstates the measured decay rate of composition waves (by 20% at
+    # (0.036, 0.704)); slope/2K falls with the vapour's rho_A across all four
+    # cases (0.94, 0.90, 0.875, 0.87), so it shares the wider band.
+    assert abs(ratio - 1) < (0.15 if rho_h in (0.035, 0.045) else 0.10)
 
 
 @pytest.fixture(scope="module")
@@ -183,3 +193,81 @@ def test_droplet_shrinks_like_the_radius_odes(lb, surface_tension):
     # coefficient overestimates the measured decay rate of composition waves
     # at this asymmetric composition).
     assert err_plain < 1.0
+
+
+def interface_radius(ra, r, mid):
+    """Radius where the shell-averaged rho_A crosses mid (linear
+    interpolation between 0.5-wide radial bins)."""
+    k = (r / 0.5).astype(int).ravel()
+    cnt = np.bincount(k)
+    ok = cnt > 0   # the innermost bins hold no node
+    prof = (np.bincount(k, weights=ra.ravel())[ok] / cnt[ok])
+    rc = np.bincount(k, weights=r.ravel())[ok] / cnt[ok]
+    i = int(np.argmax(prof < mid))
+    assert i > 0 and prof[i] < mid <= prof[i - 1]
+    return float(np.interp(mid, [prof[i], prof[i - 1]], [rc[i], rc[i - 1]]))
+
+
+def test_droplet_grows_by_condensation(lb, surface_tension):
+    """The sink set above the minority density (rho_H = 0.05 > rho_mi ~ 0.04)
+    feeds vapour to the droplet: R(t) grows and follows the same sign-fixed
+    laws, now with dM/dt > 0 (Sec. II C; the condensation case of the
+    outlook in Sec. IV). R is the radial crossing of rho_A through the
+    midpoint of the bulk densities: the phase-field volume of the
+    diagnostics would also count the vapour's rise towards rho_H."""
+    gamma = surface_tension[0]
+    n, R0, RH, rho_h = 64, 12.0, 31.0, 0.05
+    p = lb.make_params(n, n, n, g=3.6, psi="exp", precision="fp64", sink="none", rho_h=rho_h, sink_radius=RH,
+                       phi_delta=(0.675, -0.675))
+    sim = lb.Sim(p)
+    sim.set_graph(100)
+    a, b = li.droplet(n, n, n, R0)
+    sim.init_from_density(a, b)
+    sim.step(4000)
+    ra = sim.density(0).cpu().numpy()
+    rb = sim.density(1).cpu().numpy()
+    c = n // 2
+    rho_ma0 = ra[c - 2:c + 2, c - 2:c + 2, c - 2:c + 2].mean()
+    zz, yy, xx = np.meshgrid(*(np.arange(n) - (n - 1) / 2,) * 3, indexing="ij")
+    r = np.sqrt(xx ** 2 + yy ** 2 + zz ** 2)
+    shell = (r > 27) & (r < 30)
+    rho_mi0 = ra[shell].mean()
+    rho_t = (ra + rb)[shell].mean()
+    assert rho_h > rho_mi0 + 0.005
+    mid = 0.5 * (rho_ma0 + rho_mi0)
+    sim.set_sink("sphere", rho_h, RH)
+    r_start = interface_radius(sim.density(0).cpu().numpy(), r, mid)
+    ts, rs = [0.0], [r_start]
+    for k in range(40):
+        sim.step(500)
+        assert sim.diagnostics()["nonfinite"] == 0
+        ts.append(500.0 * (k + 1))
+        rs.append(interface_radius(sim.density(0).cpu().numpy(), r, mid))
+        if rs[-1] > 18:
+            break
+    ts, rs = np.array(ts), np.array(rs)
+    ram = 0.5 * (rho_mi0 + rho_h)
+    D = an.diffusion_small_gradient(ram, rho_t - ram, 3.6, "exp")
+    d0 = 2.5
+    t_plain, r_plain = an.rk4(lambda R: an.droplet_rate_plain(R, RH, d0, D, rho_ma0, rho_mi0, rho_h),
+                              r_start, ts[-1], 50.0)
+    t_lap, r_lap = an.rk4(lambda R: an.droplet_rate_laplace(R, RH, d0, D, r_start, gamma, rho_ma0, rho_mi0, rho_h),
+                          r_start, ts[-1], 50.0)
+    plain = np.interp(ts, t_plain, r_plain)
+    lap = np.interp(ts, t_lap, r_lap)
+    err_plain = np.max(np.abs(rs - plain))
+    err_lap = np.max(np.abs(rs - lap))
+    print(f"R: {np.round(rs[::4], 2)}\nplain: {np.round(plain[::4], 2)}\nlaplace: {np.round(lap[::4], 2)}")
+    print(f"max |R - law| plain={err_plain:.3f} laplace={err_lap:.3f} gamma={gamma:.4f} D={D:.4f}")
+    growth = (rs[-1] - r_start) / (plain[-1] - r_start)
+    print(f"growth against the plain law: {growth:.3f}")
+    assert rs[-1] > r_start + 2, "droplet must grow"
+    # monotone once the sink's vapour front has crossed the 19-node gap to
+    # the droplet (a diffusion time of ~19^2 / D ~ 3e3 steps; in the first
+    # 500 steps the droplet still relaxes by a few 1e-3)
+    assert np.all(np.diff(rs[ts >= 500]) > 0)
+    # the same bar as the evaporating droplet: within one lattice unit; the
+    # rate within the 20% by which the small-gradient D^c overstates the
+    # composition decay rate at this vapour composition
+    assert err_plain < 1.0
+    assert 0.8 <= growth <= 1.05
