@@ -1,10 +1,13 @@
-"""Closed forms of the paper used to pin the oracle (test infrastructure only).
+"""Closed forms of the paper, and a finite-difference Fick reference, used to
+pin the oracle and the GPU physics (test infrastructure only).
 
 All in lattice units with c_s^2 = 1/3 and tau = 1 unless given.
 """
 from __future__ import annotations
 
 import math
+
+import numpy as np
 
 CS2 = 1.0 / 3.0
 
@@ -120,3 +123,18 @@ def rk4(rate, y0: float, t_end: float, dt: float):
         ts.append(t)
         ys.append(y)
     return ts, ys
+
+
+def fick_bath_fd(nz: int, rho_h: float, D: float, T: float, dt: float = 0.05):
+    """Explicit finite-difference solution of Fick's second law (Eq. (fick2))
+    on nz nodes for the diffusion test of Sec. III A: the last node held at
+    rho_H, a zero-flux mirror half a node below node 0 (a half-way
+    bounce-back wall), zero initial density, integrated to time T."""
+    u = np.zeros(nz)
+    u[-1] = rho_h
+    for _ in range(int(round(T / dt))):
+        lap = np.empty(nz - 1)
+        lap[1:] = u[2:] - 2 * u[1:-1] + u[:-2]
+        lap[0] = u[1] - u[0]
+        u[:-1] += dt * D * lap
+    return u

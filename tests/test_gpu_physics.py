@@ -95,6 +95,26 @@ def test_film_sqrt_t_law_paper_length(lb, film_state, rho_h):
     assert abs(ratio - 1) < (0.15 if rho_h in (0.035, 0.045) else 0.10)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32s"])
+def test_diffusion_into_bath_gpu(lb, precision):
+    """Sec. III A on the GPU: the diffusing component invades a box of its
+    partner (rho = 0.7) from an evaporation boundary held at rho_H = 0.001,
+    as the finite-difference solution of Fick's second law with the
+    coefficient of Eq. (diffu-t-1) predicts (the bar of the oracle pin: 0.5%
+    of rho_H)."""
+    nz, rho_h, T = 125, 0.001, 8000
+    sim = lb.Sim(lb.make_params(4, 4, nz, wall_z=True, g=3.6, psi="exp", precision=precision, sink="zmax",
+                                rho_h=rho_h, shift=(0.0, 0.7)))
+    sim.init_from_density(np.zeros((nz, 4, 4)), np.full((nz, 4, 4), 0.7))
+    sim.step(T)
+    ra = sim.density(0).cpu().numpy()
+    u = an.fick_bath_fd(nz, rho_h, an.diffusion_small_gradient(0.5 * rho_h, 0.7, 3.6, "exp"), T)
+    err = np.max(np.abs(ra[:, 0, 0] - u)) / rho_h
+    print(f"{precision}: max |rho_A - Fick| = {err:.2e} of rho_H")
+    assert np.ptp(ra, axis=(1, 2)).max() < (1e-15 if precision == "fp64" else 1e-9)
+    assert err < 0.005
+
+
 @pytest.fixture(scope="module")
 def surface_tension(lb):
     """gamma from static droplets: P_in - P_out = 2 gamma / R, with the

@@ -279,14 +279,8 @@ def test_diffusion_into_bath_follows_ficks_law():
     o = Oracle(OracleParams(4, 4, nz, wall_z=True, g=3.6, psi=PSI_EXP, sink=SINK_ZMAX, rho_h=rho_h))
     o.init_from_density(np.zeros((nz, 4, 4)), np.full((nz, 4, 4), 0.7))
     D = an.diffusion_small_gradient(0.5 * rho_h, 0.7, 3.6, "exp")
-    T, dt = 8000, 0.05
-    u = np.zeros(nz)
-    u[-1] = rho_h
-    for _ in range(int(T / dt)):
-        lap = np.empty(nz - 1)
-        lap[1:] = u[2:] - 2 * u[1:-1] + u[:-2]
-        lap[0] = u[1] - u[0]
-        u[:-1] += dt * D * lap
+    T = 8000
+    u = an.fick_bath_fd(nz, rho_h, D, T)
     o.step(T)
     ra = o.density()[0]
     assert np.ptp(ra, axis=(1, 2)).max() < 1e-15   # planar
