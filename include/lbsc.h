@@ -86,8 +86,9 @@ typedef struct lbsc_params {
     double shift[2];         /* rho0^c of shifted storage (ignored for FP64) */
     int32_t sink;            /* LBSC_SINK_* */
     int32_t plane_pad;       /* extra elements between population planes
-                                (>= 0; spreads the 38 plane streams over HBM
-                                channels); 0 = none */
+                                (>= 0; spreads the plane streams over HBM
+                                channels: 38 per slab for FP32S, 19 planes
+                                of (A, B) pairs for FP64 and FP16); 0 = none */
     double rho_h;            /* density imposed on A at sink nodes */
     double sink_radius;      /* LBSC_SINK_SPHERE only */
     double center[3];        /* sphere centre (x, y, z) in node units */
@@ -118,10 +119,12 @@ typedef struct lbsc_ctx lbsc_ctx;
  * kernel variant: 1 keeps a node's pulled populations in registers from its
  * density pass to its collision, 2 pulls the node again for the collision
  * (fewer registers, more blocks per CU), 3 (FP64 with nt = 256, FP32S,
- * FP16S) also keeps them but issues each plane's loads one plane ahead of
- * use, with one barrier per plane; it needs one thread per halo node of a
+ * FP16S, FP16N) also keeps them but issues each plane's loads one plane ahead
+ * of use, with one barrier per plane; it needs one thread per halo node of a
  * tile (the halo of a tile spanning the whole x or y extent is the tile
- * itself), so tiles that break this are rejected. Variants give bitwise
+ * itself), and for FP16N (tw + 4)(th + 4) <= 3 nt (the rest values of the
+ * tile and two halo rings are staged through LDS), so tiles that break this
+ * are rejected. Variants give bitwise
  * identical populations. Zero or negative fields mean "choose automatically"
  * (variant: 3 where it applies, else 1). */
 typedef struct lbsc_tiles {

@@ -346,6 +346,28 @@ __device__ __forceinline__ void pull_raw(const typename S::T* __restrict__ src, 
     }
 }
 
+// FP16N moving values alone: the pipelined step takes the rest values of the
+// source nodes from an LDS ring rather than with 19 loads per node.
+template <class S> struct RawH {
+    typename S::T h[2][kQ];
+};
+
+// Issues the loads of the moving values of the pull of node (x, y, z).
+template <class S>
+__device__ __forceinline__ void pull_h(const typename S::T* __restrict__ src, const Inst& I, int x, int y, int z,
+                                       RawH<S>& w)
+{
+    using T = typename S::T;
+    static_assert(S::kNode, "per-node rest encodings only");
+    const PullAddr<S> a(src, I, x, y, z);
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) {
+        const Pair<T> h = bload2<T>(a.rsrc(i), a.xy(i) * pair_bytes<S>(i), pair_off<S>(a.q(i), a.ps));
+        w.h[0][i] = h.a;
+        w.h[1][i] = h.b;
+    }
+}
+
 // Decodes the raw values into deviations f_i - w_i rho0.
 template <class S, typename A = typename S::A>
 __device__ __forceinline__ void decode_raw(const RawNode<S>& w, NodeVals<A>& v)
@@ -777,6 +799,14 @@ __host__ __device__ inline void pipe_stencil(int a, int w, bool per, int out[3])
     out[2] = per && a == w - 1 ? 1 : a + 2;
 }
 
+// FP16N in the pipelined step: the rest pairs of the tile plus two halo
+// rings ((tw + 4)(th + 4) nodes: every source of a tile or halo node's pull)
+// are staged per plane into LDS, at most kRestLoads per thread.
+constexpr int kRestLoads = 3;
+__host__ __device__ inline bool rest_fits(int tw, int th, int nt) { return (tw + 4) * (th + 4) <= kRestLoads * nt; }
+
+__host__ __device__ inline int mod_n(int a, int n) { return ((a % n) + n) % n; }
+
 // Waves per SIMD the pipelined step is compiled for: two in FP32 arithmetic
 // (<= 256 VGPRs); one in FP64, whose three population sets take ~490.
 template <class St> constexpr int kPipeWaves = std::is_same_v<typename St::A, double> ? 1 : 2;
@@ -793,9 +823,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<S
     // three sets rotate (collided / decoded / in flight). Otherwise the loads
     // land in a raw set that is decoded into one of two sets.
     constexpr bool kRotate = std::is_same_v<T, A> && !St::kNode;
+    // FP16N: the sources' FP32 rest pairs come from a four-plane LDS ring.
+    constexpr bool kLdsRest = St::kNode;
     constexpr int FP = Foot<NT>::kMax;
     __shared__ A psiS[4][2][FP];
     __shared__ double red[NT / 64];
+    __shared__ F2 restS[kLdsRest ? 4 : 1][kLdsRest ? kRestLoads * NT : 1];
 
     const int k = xcd_item(blockIdx.x, n_items);
     if (k >= n_items) return;
@@ -815,7 +848,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<S
     // where they are used: held in registers across the march they would
     // crowd out the population sets, and the compiler would hoist the
     // address arithmetic derived from them out of the march as well.
-    __shared__ uint32_t tinfo[7][NT];
+    __shared__ uint32_t tinfo[kLdsRest ? 8 + kRestLoads : 7][NT];
     {
         const int tx = own ? t % tw : 0, ty = own ? t / tw : 0;
         const int x = wrap(it.x0 + tx, I.nx), y = wrap(it.y0 + ty, I.ny);
@@ -831,6 +864,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<S
         tinfo[4][t] = sink_zrange(I.reset, x, y, I.nx, I.ny, I.nz);
         tinfo[5][t] = sink_zrange(I.cur, x, y, I.nx, I.ny, I.nz);
         tinfo[6][t] = sink_zrange(I.reset, hx, hy, I.nx, I.ny, I.nz);
+        if constexpr (kLdsRest) {
+            // rest footprint positions: this thread's tile and halo nodes,
+            // and the in-plane index of the nodes it stages. Positions past
+            // the footprint stage node 0 into ring entries nothing reads, so
+            // the staging runs without divergent branches around its loads
+            // (whose joins would make the compiler wait for every load).
+            const int W = tw + 4, nfp = W * (th + 4);
+            tinfo[7][t] = pack((ty + 2) * W + tx + 2, (fy + 2) * W + fx + 2);
+#pragma unroll
+            for (int j = 0; j < kRestLoads; ++j) {
+                const int p = t + j * NT;
+                uint32_t v = 0;
+                if (p < nfp) {
+                    const int gx = mod_n(it.x0 + p % W - 2, I.nx), gy = mod_n(it.y0 + p / W - 2, I.ny);
+                    v = (uint32_t)gy * (uint32_t)I.nx + (uint32_t)gx;
+                }
+                tinfo[8 + j][t] = v;
+            }
+        }
     }
     auto lo = [](uint32_t v) { return (int)(v & 0xffffu); };
     auto hi = [](uint32_t v) { return (int)(v >> 16); };
@@ -862,21 +914,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<S
         if (zq <= z1 && ring) pull_raw<St>(s, I, lo(h), hi(h), psi_plane(zs + dz * zq, I.nz, I.wall_z), wr);
     };
     auto issue_own = [&](int zq, T (&wo)[2][kQ]) {
-        const uint32_t o = tinfo[0][t];
-        if (zq <= z1) pull_vals<St>(s, I, lo(o), hi(o), psi_plane(zs + dz * zq, I.nz, I.wall_z), wo);
+        if constexpr (!St::kNode) {
+            const uint32_t o = tinfo[0][t];
+            if (zq <= z1) pull_vals<St>(s, I, lo(o), hi(o), psi_plane(zs + dz * zq, I.nz, I.wall_z), wo);
+        }
     };
     // Densities (with the pull-time sink reset) of logical plane zq: psi of
     // the halo node from wr and of the tile node from v (decoded, reset in
     // place) into the plane's LDS slot; the flux of reset tile nodes is
     // booked.
-    auto dens = [&](int zq, const RawNode<St>& wr, NodeVals<A>& v) {
+    auto dens_with = [&](int zq, auto&& ring_decode, NodeVals<A>& v) {
         const int zp = psi_plane(zs + dz * zq, I.nz, I.wall_z);
         A(*ps)[FP] = psiS[(zq - z0 + 1) & 3];
         const uint32_t fi = tinfo[2][t];
         double fl = 0.0;
         if (ring) {
             NodeVals<A> h;
-            decode_raw<St>(wr, h);
+            ring_decode(h);
             node_density<A>(I, h);
             if (in_zrange_sink(tinfo[6][t], zp)) sink_reset<A>(I, h);
             ps[0][hi(fi)] = psi_of<A>(h.rho[0], I.psi_exp);
@@ -890,6 +944,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<S
         }
         if (book && zq >= z0 && zq < z1 && __builtin_amdgcn_ballot_w64(fl != 0.0))
             ewave = wave_uniform(ewave + block_sum_wave(fl));
+    };
+    auto dens = [&](int zq, const RawNode<St>& wr, NodeVals<A>& v) {
+        dens_with(zq, [&](NodeVals<A>& h) { decode_raw<St>(wr, h); }, v);
     };
     auto collide = [&](int m, NodeVals<A>& v) {
         if (!own) return;
@@ -950,6 +1007,118 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<S
             if (z + 2 >= z1) break;
             step(z + 2, p2, p1);
             if (z + 3 >= z1) break;
+        }
+    } else if constexpr (kLdsRest) {
+        // Rest pairs of stored logical plane q (physical plane zs + dz q,
+        // wrapped, or clamped at a wall: planes past a wall are never
+        // sources) into registers, then into ring slot (q + 2) & 3. Plane q
+        // is staged with the loads of plane q - 2 and written before the
+        // barrier ahead of the decode of plane q - 1, its first reader; the
+        // slot it takes last held plane q - 4, whose last reader (the decode
+        // of plane q - 3) is behind that barrier's predecessor.
+        auto stage_issue = [&](int q, F2 (&sv)[kRestLoads]) {
+            if (q > z1 + 1) return;
+            const int zr = zs + dz * q;
+            // the plane is the same on every lane: say so, or the integer
+            // modulo (vector-only) makes the resource look divergent
+            const int zp = __builtin_amdgcn_readfirstlane(I.wall_z ? min(max(zr, 0), I.nz - 1) : mod_n(zr, I.nz));
+            const Rsrc r = slab_rsrc(s + (int64_t)zp * I.slab);
+            const uint32_t off = pair_off<St>(0, (uint32_t)I.ps);
+#pragma unroll
+            for (int j = 0; j < kRestLoads; ++j) {
+                const Pair<float> pr = bload2<float>(r, tinfo[8 + j][t] * pair_bytes<St>(0), off);
+                sv[j] = F2{pr.a, pr.b};
+            }
+        };
+        auto stage_write = [&](int q, const F2 (&sv)[kRestLoads]) {
+            if (q > z1 + 1) return;
+            F2* slot = restS[(q + 2) & 3];
+#pragma unroll
+            for (int j = 0; j < kRestLoads; ++j) slot[t + j * NT] = sv[j];
+        };
+        auto stage_now = [&](int q) {
+            F2 sv[kRestLoads];
+            stage_issue(q, sv);
+            stage_write(q, sv);
+        };
+        // Decode of the moving values w of logical plane m at rest footprint
+        // position b: each population's source rest value from the ring, the
+        // same arithmetic as decode_raw. A halo plane mirrored at a wall pulls
+        // exactly like the plane next to it.
+        auto decode_lds = [&](int m, uint32_t b, const RawH<St>& w, NodeVals<A>& v) {
+            const int zr = zs + dz * m;
+            const int me = (I.wall_z && (zr < 0 || zr >= I.nz)) ? (m < z0 ? z0 : z1 - 1) : m;
+            const int zp = zs + dz * me;
+            const bool wlo = I.wall_z && zp == 0, whi = I.wall_z && zp == I.nz - 1;
+            const int W = tw + 4;
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                const int e = ez(i);
+                const bool refl = (e > 0 && wlo) || (e < 0 && whi);
+                const F2 d = (i == 0 || refl) ? restS[(me + 2) & 3][b]
+                                              : restS[(me - dz * e + 2) & 3][(int)b - ey(i) * W - ex(i)];
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    v.f[c][i] = i == 0 ? d[c] : kRatio(i) * d[c] + (float)w.h[c][i];
+            }
+        };
+        RawH<St> ro, rr;
+        NodeVals<A> va, vb;
+        auto issue_into = [&](int zq, RawH<St>& wo, RawH<St>& wr) {
+            if (zq > z1) return;
+            const int zp = psi_plane(zs + dz * zq, I.nz, I.wall_z);
+            const uint32_t h = tinfo[1][t], o = tinfo[0][t];
+            // the tile node first: the slab pointers it derives (branches on
+            // the wall) are then formed outside the halo lanes' divergent
+            // region, where the compiler would take them as divergent and
+            // wrap every load in a loop over their values
+            pull_h<St>(s, I, lo(o), hi(o), zp, wo);
+            if (ring) pull_h<St>(s, I, lo(h), hi(h), zp, wr);
+        };
+        auto dens_from = [&](int zq, NodeVals<A>& keep, const RawH<St>& wo, const RawH<St>& wr) {
+            const uint32_t fb = tinfo[7][t];
+            decode_lds(zq, lo(fb), wo, keep);
+            dens_with(zq, [&](NodeVals<A>& h) { decode_lds(zq, hi(fb), wr, h); }, keep);
+        };
+        // Prologue: rest planes -2 .. 1, the densities of planes -1 and 0,
+        // then rest planes 2 and 3 into the slots of -2 and -1.
+        {
+            RawH<St> ro2, rr2;
+            stage_now(z0 - 2);
+            stage_now(z0 - 1);
+            stage_now(z0);
+            stage_now(z0 + 1);
+            __syncthreads();
+            issue_into(z0 - 1, ro2, rr2);
+            issue_into(z0, ro, rr);
+            dens_from(z0 - 1, va, ro2, rr2);
+            issue_into(z0 + 1, ro2, rr2);
+            dens_from(z0, va, ro, rr);
+            __syncthreads();
+            stage_now(z0 + 2);
+            stage_now(z0 + 3);
+            __syncthreads();
+            issue_into(z0 + 2, ro, rr);
+            dens_from(z0 + 1, vb, ro2, rr2);
+        }
+        F2 sv[kRestLoads];
+        for (int z = z0;; z += 2) {
+            __syncthreads();
+            stage_issue(z + 4, sv);
+            collide(z, va);
+            dens_from(z + 2, va, ro, rr);
+            stage_write(z + 4, sv);
+            __builtin_amdgcn_sched_barrier(0);
+            issue_into(z + 3, ro, rr);
+            if (z + 1 >= z1) break;
+            __syncthreads();
+            stage_issue(z + 5, sv);
+            collide(z + 1, vb);
+            dens_from(z + 3, vb, ro, rr);
+            stage_write(z + 5, sv);
+            __builtin_amdgcn_sched_barrier(0);
+            issue_into(z + 4, ro, rr);
+            if (z + 2 >= z1) break;
         }
     } else {
         RawNode<St> ro, rr;

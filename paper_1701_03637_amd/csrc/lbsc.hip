@@ -226,8 +226,6 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
     const int target_items = f64 ? 256 : 4096;
     if (nt != 256 && nt != 512) return fail(c, LBSC_E_ARG, "tiles.nt must be 256 or 512");
     if (t.variant > 3) return fail(c, LBSC_E_ARG, "tiles.variant must be 0, 1, 2 or 3");
-    if (t.variant == 3 && c->precision == LBSC_FP16N)
-        return fail(c, LBSC_E_ARG, "tiles.variant 3 needs FP64, FP32S or FP16S storage");
     if (t.variant == 3 && c->precision == LBSC_FP64 && nt != 256)
         return fail(c, LBSC_E_ARG, "tiles.variant 3 in FP64 runs 256-thread blocks");
     if (t.tw > 512 || t.th > 512) return fail(c, LBSC_E_ARG, "tiles.tw and tiles.th must be <= 512");
@@ -236,7 +234,7 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
     // width stays cheaper down to 3 rows for the pipelined step (2-row tiles
     // pulled twice their nodes and lost to 64 x 4 in FP64). The
     // register-keeping steps pay more per halo pull and run best on 8 rows.
-    const bool pipe_ok = c->precision == LBSC_FP32S || c->precision == LBSC_FP16S || (f64 && nt == 256);
+    const bool pipe_ok = !f64 || nt == 256;
     const int want = t.variant > 0 ? t.variant : (pipe_ok ? 3 : 1);
     const int min_rows = want == 3 ? 3 : 8;
     int64_t total = 0;
@@ -260,9 +258,12 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
             it.z0 + it.nzc > I.nz || it.tw < 1 || it.th < 1 || it.nzc < 1)
             return fail(c, LBSC_E_ARG, "internal: tile outside its lattice");
         if (lbsc::pipe_tile(it.tw, it.th, I.nx, I.ny).nring > nt) pipe_fits = false;
+        if (c->precision == LBSC_FP16N && !lbsc::rest_fits(it.tw, it.th, nt)) pipe_fits = false;
     }
     if (t.variant == 3 && !pipe_fits)
-        return fail(c, LBSC_E_ARG, "tiles.variant 3: a tile has more halo nodes than the %d threads", nt);
+        return fail(c, LBSC_E_ARG,
+                    "tiles.variant 3: a tile has more halo nodes than the %d threads%s", nt,
+                    c->precision == LBSC_FP16N ? ", or (tw + 4)(th + 4) exceeds 3 nt (FP16N rest footprint)" : "");
     variant = t.variant > 0 ? t.variant : (pipe_fits ? 3 : 1);
     if (variant != 3)
         for (auto& it : items) it.down = 0;  // the register-keeping steps march upwards only
@@ -329,7 +330,7 @@ hipError_t launch_step_p(lbsc_ctx* c, hipStream_t s, int src)
 {
     if constexpr (std::is_same_v<typename St::A, double>) {
         if (c->variant == 3) return launch_pipe_t<St, 256>(c, s, src);  // one wave per SIMD: 256 threads only
-    } else if constexpr (!St::kNode) {
+    } else {
         if (c->variant == 3)
             return c->nt == 512 ? launch_pipe_t<St, 512>(c, s, src) : launch_pipe_t<St, 256>(c, s, src);
     }
@@ -706,7 +707,7 @@ lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
     for (int variant : {1, 2, 3})
         for (int nt : {256, 512}) {
             if (nt == 512 && c->precision == LBSC_FP64 && variant == 1) continue;  // exceeds the register file
-            if (variant == 3 && (c->precision == LBSC_FP16N || (c->precision == LBSC_FP64 && nt != 256)))
+            if (variant == 3 && c->precision == LBSC_FP64 && nt != 256)
                 continue;
             for (int tw : {0, 32, 64, 128})
                 for (int nzc : {0, 8, 16, 32, 64}) cands.push_back(lbsc_tiles{nt, tw, 0, nzc, variant});

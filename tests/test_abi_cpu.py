@@ -84,9 +84,9 @@ def test_tile_schedule_errors(lib):
 
 def test_kernel_variant_resolution(lib):
     """Variant 0 resolves to the pipelined step where every tile's halo has a
-    thread per node and the storage is FP32S / FP16S, or FP64 in 256-thread
-    blocks, else to the register-keeping step; an explicit variant 3 that
-    does not fit fails."""
+    thread per node (and, for FP16N, the rest footprint fits) and the storage
+    is FP32S / FP16S / FP16N, or FP64 in 256-thread blocks, else to the
+    register-keeping step; an explicit variant 3 that does not fit fails."""
     from paper_1701_03637_amd import lbsc
 
     def resolve(prec, n, tiles):
@@ -104,13 +104,14 @@ def test_kernel_variant_resolution(lib):
     assert resolve("fp64", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 256, 3)
     assert resolve("fp64", (128, 128, 128), (512, 0, 0, 0, 0)) == (0, 512, 1)
     assert resolve("fp64", (128, 128, 128), (512, 0, 0, 0, 3))[0] == -1
-    assert resolve("fp16n", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 512, 1)
+    assert resolve("fp16n", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 512, 3)
     # 128 x 2 tiles of a 256-wide lattice: 2 (128 + 2) + 2 x 2 = 264 halo nodes
     assert resolve("fp32s", (256, 64, 32), (256, 128, 2, 0, 0)) == (0, 256, 1)
     rc, _, _ = resolve("fp32s", (256, 64, 32), (256, 128, 2, 0, 3))
     assert rc == -1
     assert resolve("fp32s", (256, 64, 32), (512, 128, 4, 0, 3)) == (0, 512, 3)
-    assert resolve("fp16n", (64, 64, 64), (256, 64, 4, 0, 3))[0] == -1
+    assert resolve("fp16n", (64, 64, 64), (256, 64, 4, 0, 3)) == (0, 256, 3)
+    assert resolve("fp16n", (256, 64, 32), (256, 128, 2, 0, 3))[0] == -1
 
 
 
@@ -123,10 +124,12 @@ def test_default_tiles_split_evenly(lib):
     threads: 64 tiles of 64 x 4 in 4 chunks)."""
     from paper_1701_03637_amd import lbsc
 
-    def items(n, prec):
+    def items(n, prec, tiles=None):
         h = ctypes.c_void_p()
         p = lbsc.make_params(*n, precision=prec)
         assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == 0
+        if tiles is not None:
+            assert lib.lbsc_set_tiles(h, ctypes.byref(lbsc.Tiles(*tiles))) == 0
         v = ctypes.c_int32()
         assert lib.lbsc_num_items(h, ctypes.byref(v)) == 0
         lib.lbsc_destroy(h)
@@ -139,4 +142,6 @@ def test_default_tiles_split_evenly(lib):
     # cases where full-width tiles would be too thin
     assert items((200, 9, 16), "fp32s") == 2 * 2     # 100 x 5 (full width: 2 rows, 5 tiles)
     assert items((100, 9, 16), "fp64") == 2 * 2      # 50 x 5 (full width: 2 rows, 5 tiles)
-    assert items((100, 11, 16), "fp16n") == 2 * 2    # 50 x 10 (full width: 5 rows, 3 tiles)
+    # the keep step asks for 8 rows
+    assert items((100, 11, 16), "fp16n", (512, 0, 0, 0, 1)) == 2 * 2    # 50 x 10 (full width: 5 rows, 3 tiles)
+    assert items((100, 11, 16), "fp16n") == 3                           # pipelined: full width, 5 rows

@@ -172,16 +172,19 @@ PIPE_CASES = [
 
 
 @pytest.mark.parametrize("case", PIPE_CASES)
-@pytest.mark.parametrize("precision", ["fp32s", "fp16s", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32s", "fp16s", "fp64", "fp16n"])
 def test_pipelined_variant_bitwise_identical(lb, case, precision):
     """The pipelined step (one plane of loads ahead, four psi slots, halo
-    wrapped inside tiles that span x or y, chunks marching up and down)
-    gives the same bits as the register-keeping step, and books the same
-    evaporated mass; one case has tau^A != tau^B and a spherical sink."""
+    wrapped inside tiles that span x or y, chunks marching up and down; FP16N
+    with its rest values through an LDS ring) gives the same bits as the
+    register-keeping step, and books the same evaporated mass; one case has
+    tau^A != tau^B and a spherical sink."""
     (nx, ny, nz), wall, sink, tiles = case[:4]
     tau = case[4] if len(case) > 4 else (1.0, 1.0)
     if precision == "fp64" and tiles[0] != 256:
         pytest.skip("the FP64 pipelined step runs 256-thread blocks")
+    if precision == "fp16n" and tiles[1] > 0 and (tiles[1] + 4) * (tiles[2] + 4) > 3 * tiles[0]:
+        pytest.skip("the FP16N rest footprint (tw + 4)(th + 4) exceeds 3 nt")
     f0 = li.random_populations(nx, ny, nz, seed=5, base_a=0.3, base_b=0.4, amp=0.05)
 
     def run(t):
