@@ -524,7 +524,18 @@ __device__ __forceinline__ void collide_node(const Inst& I, NodeVals<A>& v, cons
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const A rho = v.rho[c];
-        const A kc = rho != (A)0 ? Par<A>::ntg(I, c) * psi[c] * recip<A>(rho) : (A)0;
+        // k^c = -tau^c g psi^c / rho^c. In FP32, psi = rho gives psi / rho = 1
+        // exactly; for psi = 1 - exp(-rho) the reciprocal overflows below the
+        // smallest normal density, where psi / rho takes its limit 1. At
+        // rho = 0, f^eq vanishes whatever the velocity.
+        A kc;
+        if constexpr (kPlain<A>)
+            kc = rho != (A)0 ? Par<A>::ntg(I, c) * psi[c] * recip<A>(rho) : (A)0;
+        else if (!I.psi_exp)
+            kc = Par<A>::ntg(I, c);
+        else
+            kc = __builtin_fabsf(rho) >= __FLT_MIN__ ? Par<A>::ntg(I, c) * psi[c] * recip<A>(rho)
+                                                      : (rho != (A)0 ? Par<A>::ntg(I, c) : (A)0);
         const A u[3] = {up[0] + kc * S[c][0], up[1] + kc * S[c][1], up[2] + kc * S[c][2]};
         const A uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
         const A drho = v.drho[c];
