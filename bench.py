@@ -16,6 +16,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -31,10 +32,15 @@ DTYPE = {"fp64": "f64", "fp32s": "f32", "fp16s": "f32", "fp16n": "f32"}
 
 
 def kernel_hash() -> str:
+    """Hash of the kernel sources' code: comments and whitespace are dropped,
+    so a counter record stays valid across edits that change no code."""
     h = hashlib.sha256()
     for f in ("kernels.h", "lattice.h", "lbsc.hip"):
-        with open(os.path.join(ROOT, "paper_1701_03637_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1701_03637_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

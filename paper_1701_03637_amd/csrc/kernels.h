@@ -16,9 +16,9 @@
 //   f_i(x) = f*_i(x - e_i), or f*_opp(i)(x) across a z-seam wall,
 // followed by the sink reset of the sink that was active when S(t) formed.
 // Storage forms (policies St* below):
-//   FP64    38 planes of f, FP64 arithmetic;
+//   FP64    f in 19 planes of (A, B) pairs, FP64 arithmetic;
 //   FP32S   38 planes of f - w_i rho0^c (constant shift), FP32 arithmetic;
-//   FP16S   the same deviations in FP16, FP32 arithmetic;
+//   FP16S   the same deviations in FP16, 19 pair planes, FP32 arithmetic;
 //   FP16N   per-node shift: the rest deviation d_0 = f_0 - w_0 rho0 in FP32
 //           and the 18 moving deviations as h_i = d_i - k_i d_0 of the same
 //           node in FP16, k_i = w_i / w_0 (h = 0 at rest equilibrium), FP32
@@ -27,10 +27,11 @@
 // (rho0 = 0 for FP64).
 //
 // Fused step (one launch per time step): a block owns an xy tile and marches
-// along z with a three-plane ring of psi (tile plus a one-node halo) in LDS.
-// Each tile node is pulled once per step into registers; halo nodes are
-// pulled only to form their density. Collision reads the 18 neighbour psi
-// values from LDS and writes f* aligned to the other buffer.
+// along z with a ring of psi planes (tile plus a one-node halo) in LDS: three
+// for the register-keeping step, four for the pipelined one. Each tile node
+// is pulled once per step into registers; halo nodes are pulled only to form
+// their density. Collision reads the 18 neighbour psi values from LDS and
+// writes f* aligned to the other buffer.
 #pragma once
 
 #include <hip/hip_runtime.h>
