@@ -287,3 +287,27 @@ def test_reduced_precision_droplet_against_oracle(lb, precision, tol):
     dg, do = sim.diagnostics(), orc.diagnostics()
     tot = do["mass"][0] + do["mass"][1]
     assert abs(dg["mass"][0] + dg["evaporated"] - (do["mass"][0] + do["evaporated"])) / tot < tol
+
+
+def test_tuner_leaves_a_schedule_with_identical_results(lb):
+    """lbsc_tune times every candidate schedule on the live state (re-timing
+    its three fastest) and keeps the best; what it keeps must be a valid
+    schedule giving the same bits as the default one, and the graph setting
+    must survive the tuning."""
+    nx, ny, nz = 40, 36, 32
+    p = lb.make_params(nx, ny, nz, psi="exp", g=2.0, sink="faces", rho_h=0.03, precision="fp32s")
+    sim = lb.Sim(p)
+    sim.set_graph(4)
+    a, b = li.droplet(nx, ny, nz, 8.0)
+    sim.init_from_density(a, b)
+    chosen = sim.tune(3)
+    assert sim.tiles() == chosen
+    assert chosen[0] in (256, 512) and chosen[4] in (1, 2, 3)
+    f = sim.populations()
+    ref = lb.Sim(p)
+    for s in (sim, ref):
+        s.init_from_populations(f)
+        s.step(6)
+    assert torch.equal(sim.populations(), ref.populations())
+    d = sim.diagnostics()
+    assert d["nonfinite"] == 0
