@@ -290,6 +290,46 @@ def test_diffusion_into_bath_follows_ficks_law():
 
 
 # ---------------------------------------------------------------------------
+# Diagnostics on constructed fields (x_I of Sec. III B, R_I of Sec. III C).
+# ---------------------------------------------------------------------------
+
+def test_interface_height_is_the_zero_of_a_linear_profile():
+    """x_I is the first zero of the plane mean of rhoA - rhoB scanning up from
+    z = 0, linearly interpolated: exact for a profile linear in z (here with a
+    cross-section whose plane mean, not each node, is linear)."""
+    nx, ny, nz, zs = 3, 2, 48, 20.3
+    z = np.arange(nz, dtype=float)[:, None, None]
+    wob = 0.004 * np.array([[1.0, -1.0, 0.5], [-0.5, 0.0, 0.0]])[None]   # zero mean over the plane
+    a = 0.37 - 0.01 * (z - zs) + wob + np.zeros((nz, ny, nx))
+    b = 0.37 + 0.01 * (z - zs) - wob + np.zeros((nz, ny, nx))
+    o = Oracle(_params(nx, ny, nz))
+    o.init_from_density(a, b)
+    assert abs(o.diagnostics()["z_interface"] - zs) < 1e-12
+
+
+def test_droplet_radius_of_a_sharp_droplet():
+    """R_I = (3 sum(phi) / 4 pi)^(1/3) with phi = clamp((rhoA - rhoB -
+    D_out) / (D_in - D_out), 0, 1): a droplet of bulk densities inside radius
+    R gives phi = 1 on its nodes and 0 elsewhere, so R_I is the radius of a
+    sphere of their count (brute force)."""
+    n, R = 24, 7.3
+    c = (n - 1) / 2
+    zz, yy, xx = np.meshgrid(*(np.arange(n) - c,) * 3, indexing="ij")
+    inside = xx ** 2 + yy ** 2 + zz ** 2 < R * R
+    a = np.where(inside, 0.70, 0.04)
+    b = np.where(inside, 0.04, 0.70)
+    o = Oracle(_params(n, n, n, phi_delta=(0.66, -0.66)))
+    o.init_from_density(a, b)
+    expect = (3 * inside.sum() / (4 * np.pi)) ** (1 / 3)
+    assert abs(o.diagnostics()["r_droplet"] - expect) < 1e-12
+    # halfway densities count half a node each
+    a2 = np.where(inside, 0.37, 0.04)
+    b2 = np.where(inside, 0.37, 0.70)
+    o.init_from_density(a2, b2)
+    assert abs(o.diagnostics()["r_droplet"] - (3 * 0.5 * inside.sum() / (4 * np.pi)) ** (1 / 3)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
 # Planar film (Sec. III B): coexistence and the sqrt(t) law.
 # ---------------------------------------------------------------------------
 
