@@ -291,3 +291,49 @@ def test_droplet_grows_by_condensation(lb, surface_tension):
     # composition decay rate at this vapour composition
     assert err_plain < 1.0
     assert 0.8 <= growth <= 1.05
+
+
+def _wave_diffusion(lb, precision, nz, every, amp=1e-3, mean=0.37):
+    """D from the decay of a composition wave along z: amplitude ~
+    exp(-D k^2 t) (Eq. (fick2)), fitted over 8 intervals of `every` steps."""
+    sim = lb.Sim(lb.make_params(4, 4, nz, g=0.9, psi="rho", precision=precision, shift=(mean, mean)))
+    a, b = li.sinus(4, 4, nz, mean, mean, amp)
+    sim.init_from_density(a, b)
+    s = np.sin(2 * np.pi * np.arange(nz) / nz)
+    amps, ts = [], []
+    for k in range(9):
+        if k:
+            sim.step(every)
+        ra = sim.density(0).cpu().numpy()[:, 0, 0]
+        amps.append((ra - mean) @ s / (s @ s))
+        ts.append(float(every * k))
+    slope = np.polyfit(ts[2:], np.log(amps[2:]), 1)[0]
+    return -slope / (2 * np.pi / nz) ** 2
+
+
+# A step changes a stored deviation by D k^2 of itself; FP16 resolves 2^-10 of
+# it, so FP16 storage follows the decay only where D k^2 2^10 >= 1: waves
+# shorter than ~47 nodes at D = 0.056. The 128-node wave (D k^2 2^10 = 0.35)
+# is resolved by FP32S only. On a 32-node wave (2.2) the FP16 forms follow
+# the decay but round each step's change by up to a quarter of itself: D comes
+# out 1.1 % low, just outside the 1 % bar, which is kept as the record.
+@pytest.mark.parametrize("precision,nz,every,bar", [
+    ("fp32s", 128, 500, 1e-3),
+    pytest.param("fp16n", 32, 100, 1e-2, marks=pytest.mark.xfail(
+        strict=True, reason="D k^2 2^10 = 2.2: FP16 rounding of ~2-ulp changes biases D (measured ratio 0.989)")),
+    pytest.param("fp16s", 32, 100, 1e-2, marks=pytest.mark.xfail(
+        strict=True, reason="D k^2 2^10 = 2.2: FP16 rounding of ~2-ulp changes biases D (measured ratio 0.989)")),
+    pytest.param("fp16n", 128, 500, 1e-2, marks=pytest.mark.xfail(
+        strict=True, reason="D k^2 2^10 = 0.35: per-step changes below an FP16 ulp (measured ratio 0.964)")),
+    pytest.param("fp16s", 128, 500, 1e-2, marks=pytest.mark.xfail(
+        strict=True, reason="D k^2 2^10 = 0.35: per-step changes below an FP16 ulp, the wave stagnates "
+                            "(measured ratio 0.50)")),
+])
+def test_reduced_precision_diffusion_coefficient(lb, precision, nz, every, bar):
+    """The diffusion coefficient measured through reduced-precision storage
+    matches the FP64 run's on the same wave: within 0.1 % (FP32S) and 1 % (FP16
+    forms, on waves they can resolve)."""
+    d64 = _wave_diffusion(lb, "fp64", nz, every)
+    dp = _wave_diffusion(lb, precision, nz, every)
+    print(f"{precision} nz={nz}: D = {dp:.6f}, FP64 {d64:.6f}, ratio {dp / d64:.5f}")
+    assert abs(dp / d64 - 1) < bar
