@@ -1024,10 +1024,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<S
         // Rest pairs of stored logical plane q (physical plane zs + dz q,
         // wrapped, or clamped at a wall: planes past a wall are never
         // sources) into registers, then into ring slot (q + 2) & 3. Plane q
-        // is staged with the loads of plane q - 2 and written before the
-        // barrier ahead of the decode of plane q - 1, its first reader; the
-        // slot it takes last held plane q - 4, whose last reader (the decode
-        // of plane q - 3) is behind that barrier's predecessor.
+        // is loaded at the start of the half-step decoding plane q - 2 and
+        // written at its end, before the barrier ahead of the decode of plane
+        // q - 1, its first reader; the slot it takes last held plane q - 4,
+        // whose last reader (the decode of plane q - 3) is behind the barrier
+        // that opens the half-step.
         auto stage_issue = [&](int q, F2 (&sv)[kRestLoads]) {
             if (q > z1 + 1) return;
             const int zr = zs + dz * q;
