@@ -174,9 +174,11 @@ lbsc_status lbsc_set_tiles(lbsc_ctx* ctx, const lbsc_tiles* tiles);
 /* The schedule in use: tw, th, nzc as requested (0 = automatic) and the
  * resolved nt and kernel variant. */
 lbsc_status lbsc_get_tiles(const lbsc_ctx* ctx, lbsc_tiles* out);
-/* Times candidate tile schedules for `steps` steps each and keeps the
- * fastest; writes it to *chosen if non-NULL. The populations advance during
- * tuning, so call it before lbsc_init_*. */
+/* Times candidate tile schedules (variants x nt x tile widths x chunk
+ * lengths) for `steps` steps each (steps >= 2), re-times the three fastest
+ * over 3 x steps each, and keeps the best; writes it to *chosen if non-NULL.
+ * The populations advance during tuning (every schedule gives the same
+ * bits), so call it before lbsc_init_*. The graph setting is kept. */
 lbsc_status lbsc_tune(lbsc_ctx* ctx, int32_t steps, lbsc_tiles* chosen);
 /* Number of work items (blocks per step) of the current schedule. */
 lbsc_status lbsc_num_items(const lbsc_ctx* ctx, int32_t* n_items);
