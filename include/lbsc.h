@@ -176,7 +176,8 @@ lbsc_status lbsc_set_tiles(lbsc_ctx* ctx, const lbsc_tiles* tiles);
 lbsc_status lbsc_get_tiles(const lbsc_ctx* ctx, lbsc_tiles* out);
 /* Times candidate tile schedules (variants x nt x tile widths x chunk
  * lengths) for `steps` steps each (steps >= 2), re-times the three fastest
- * over 3 x steps each, and keeps the best; writes it to *chosen if non-NULL.
+ * over three times as many steps, and keeps the best; writes it to *chosen
+ * if non-NULL.
  * The populations advance during tuning (every schedule gives the same
  * bits), so call it before lbsc_init_*. The graph setting is kept. */
 lbsc_status lbsc_tune(lbsc_ctx* ctx, int32_t steps, lbsc_tiles* chosen);
