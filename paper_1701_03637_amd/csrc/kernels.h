@@ -213,6 +213,36 @@ using H2 = _Float16 __attribute__((ext_vector_type(2)));
 using F2 = float __attribute__((ext_vector_type(2)));
 using D2 = double __attribute__((ext_vector_type(2)));
 
+template <typename A> struct Psi2T;
+template <> struct Psi2T<float> { using type = F2; };
+template <> struct Psi2T<double> { using type = D2; };
+template <typename A> using Psi2 = typename Psi2T<A>::type;
+
+// One LDS plane of psi over a tile footprint of FP nodes. PAIR keeps
+// (psi^A, psi^B) of a node together, so the force stencil reads both
+// components of a neighbour with one instruction; otherwise one plane per
+// component. Pairs measured faster for FP32S (134.6 -> 132.9 us on the 128^3
+// droplet) and FP16N, slower for FP16S (92.0 -> 95.9 us), and made the FP64
+// step spill.
+template <typename A, int FP, bool PAIR> struct PsiPlane;
+template <typename A, int FP> struct PsiPlane<A, FP, true> {
+    static constexpr bool kPair = true;
+    Psi2<A> v[FP];
+    __device__ __forceinline__ void put(int i, A a, A b) { v[i] = Psi2<A>{a, b}; }
+    __device__ __forceinline__ Psi2<A> get(int i) const { return v[i]; }
+};
+template <typename A, int FP> struct PsiPlane<A, FP, false> {
+    static constexpr bool kPair = false;
+    A v[2][FP];
+    __device__ __forceinline__ void put(int i, A a, A b)
+    {
+        v[0][i] = a;
+        v[1][i] = b;
+    }
+    __device__ __forceinline__ Psi2<A> get(int i) const { return Psi2<A>{v[0][i], v[1][i]}; }
+};
+template <class S> constexpr bool kPsiPair = std::is_same_v<S, StF32S> || std::is_same_v<S, StF16N>;
+
 template <typename T> __device__ __forceinline__ Pair<T> bload2(Rsrc r, uint32_t voff, uint32_t soff);
 template <> __device__ __forceinline__ Pair<float> bload2<float>(Rsrc r, uint32_t voff, uint32_t soff)
 {
@@ -564,25 +594,34 @@ __device__ __forceinline__ void collide_node(const Inst& I, NodeVals<A>& v, cons
 // ---------------------------------------------------------------------------
 
 // Neighbour sum of Eq. (sc) from the psi planes z-1, z, z+1 held in LDS
-// (each [2][footprint], row stride `row`): S[c] = sum_i w_i psi^{cbar}(x + e_i)
+// (footprint row stride `row`): S[c] = sum_i w_i psi^{cbar}(x + e_i)
 // e_i, taken over opposite pairs as w_i e_i times the difference of psi across
 // the node, axis and diagonal classes accumulated separately and weighted
 // once. cI[1 + e] / rI[1 + e] are the footprint column / row of the
 // neighbour at offset e in x / y.
-template <typename A, int FP>
-__device__ __forceinline__ void force_sum(const A (*pm)[FP], const A (*p0)[FP], const A (*pp)[FP], const int cI[3],
-                                          const int rI[3], int row, A S[2][3])
+template <typename A, class P>
+__device__ __forceinline__ void force_sum(const P& pm, const P& p0, const P& pp, const int cI[3], const int rI[3],
+                                          int row, A S[2][3])
 {
     A S1[2][3] = {{0, 0, 0}, {0, 0, 0}}, S2[2][3] = {{0, 0, 0}, {0, 0, 0}};
 #pragma unroll
     for (int i = 1; i < kQ; i += 2) {
-        const A(*lp)[FP] = ez(i) < 0 ? pm : (ez(i) > 0 ? pp : p0);
-        const A(*lm)[FP] = ez(i) > 0 ? pm : (ez(i) < 0 ? pp : p0);
+        const P& lp = ez(i) < 0 ? pm : (ez(i) > 0 ? pp : p0);
+        const P& lm = ez(i) > 0 ? pm : (ez(i) < 0 ? pp : p0);
         const int fp = rI[1 + ey(i)] * row + cI[1 + ex(i)];
         const int fm = rI[1 - ey(i)] * row + cI[1 - ex(i)];
+        Psi2<A> qp, qm;
+        if constexpr (P::kPair) {
+            qp = lp.get(fp);
+            qm = lm.get(fm);
+        }
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            const A dpsi = lp[1 - c][fp] - lm[1 - c][fm];
+            A dpsi;
+            if constexpr (P::kPair)
+                dpsi = qp[1 - c] - qm[1 - c];
+            else
+                dpsi = lp.v[1 - c][fp] - lm.v[1 - c][fm];
             A(&acc)[3] = i < 7 ? S1[c] : S2[c];
             if (ex(i)) acc[0] += ex(i) > 0 ? dpsi : -dpsi;
             if (ey(i)) acc[1] += ey(i) > 0 ? dpsi : -dpsi;
@@ -650,7 +689,7 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
     using T = typename St::T;
     using A = typename St::A;
     constexpr int FP = Foot<NT>::kMax;
-    __shared__ A psiS[3][2][FP];
+    __shared__ PsiPlane<A, FP, kPsiPair<St>> psiS[3];
     __shared__ double red[NT / 64];
 
     const int k = xcd_item(blockIdx.x, n_items);
@@ -688,8 +727,7 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
             node_density<A>(I, h);
             if (in_sink(I.reset, hx, hy, zp, I.nx, I.ny, I.nz)) sink_reset<A>(I, h);
             const int fi = (fy + 1) * row + fx + 1;
-            psiS[sl][0][fi] = psi_of<A>(h.rho[0], I.psi_exp);
-            psiS[sl][1][fi] = psi_of<A>(h.rho[1], I.psi_exp);
+            psiS[sl].put(fi, psi_of<A>(h.rho[0], I.psi_exp), psi_of<A>(h.rho[1], I.psi_exp));
         }
         if (own) {
             NodeVals<A> tmp;
@@ -701,8 +739,7 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
                 if (book && zq >= z0 && zq < z1) eflux += fl;
             }
             const int fi = (ty + 1) * row + tx + 1;
-            psiS[sl][0][fi] = psi_of<A>(keep.rho[0], I.psi_exp);
-            psiS[sl][1][fi] = psi_of<A>(keep.rho[1], I.psi_exp);
+            psiS[sl].put(fi, psi_of<A>(keep.rho[0], I.psi_exp), psi_of<A>(keep.rho[1], I.psi_exp));
         }
     };
 
@@ -721,9 +758,10 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
         if (!in_sink(I.cur, x, y, z, I.nx, I.ny, I.nz)) {
             const int cI[3] = {tx, tx + 1, tx + 2}, rI[3] = {ty, ty + 1, ty + 2};
             A S[2][3];
-            force_sum<A, FP>(psiS[sm], psiS[s0], psiS[sp], cI, rI, row, S);
+            force_sum<A>(psiS[sm], psiS[s0], psiS[sp], cI, rI, row, S);
             const int fc = (ty + 1) * row + tx + 1;
-            collide_node<A>(I, v, S, psiS[s0][0][fc], psiS[s0][1][fc]);
+            const Psi2<A> pc = psiS[s0].get(fc);
+            collide_node<A>(I, v, S, pc[0], pc[1]);
         }
         store_node<St>(d, I, z, xy, v);
     };
@@ -838,7 +876,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<S
     // FP16N: the sources' FP32 rest pairs come from a four-plane LDS ring.
     constexpr bool kLdsRest = St::kNode;
     constexpr int FP = Foot<NT>::kMax;
-    __shared__ A psiS[4][2][FP];
+    __shared__ PsiPlane<A, FP, kPsiPair<St>> psiS[4];
     __shared__ double red[NT / 64];
     __shared__ F2 restS[kLdsRest ? 4 : 1][kLdsRest ? kRestLoads * NT : 1];
 
@@ -937,7 +975,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<S
     // booked.
     auto dens_with = [&](int zq, auto&& ring_decode, NodeVals<A>& v) {
         const int zp = psi_plane(zs + dz * zq, I.nz, I.wall_z);
-        A(*ps)[FP] = psiS[(zq - z0 + 1) & 3];
+        auto& ps = psiS[(zq - z0 + 1) & 3];
         const uint32_t fi = tinfo[2][t];
         double fl = 0.0;
         if (ring) {
@@ -945,14 +983,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<S
             ring_decode(h);
             node_density<A>(I, h);
             if (in_zrange_sink(tinfo[6][t], zp)) sink_reset<A>(I, h);
-            ps[0][hi(fi)] = psi_of<A>(h.rho[0], I.psi_exp);
-            ps[1][hi(fi)] = psi_of<A>(h.rho[1], I.psi_exp);
+            ps.put(hi(fi), psi_of<A>(h.rho[0], I.psi_exp), psi_of<A>(h.rho[1], I.psi_exp));
         }
         node_density<A>(I, v);
         if (own && in_zrange_sink(tinfo[4][t], zp)) fl = sink_reset<A>(I, v);
         if (own) {
-            ps[0][lo(fi)] = psi_of<A>(v.rho[0], I.psi_exp);
-            ps[1][lo(fi)] = psi_of<A>(v.rho[1], I.psi_exp);
+            ps.put(lo(fi), psi_of<A>(v.rho[0], I.psi_exp), psi_of<A>(v.rho[1], I.psi_exp));
         }
         if (book && zq >= z0 && zq < z1 && __builtin_amdgcn_ballot_w64(fl != 0.0))
             ewave = wave_uniform(ewave + block_sum_wave(fl));
@@ -975,8 +1011,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<S
             // roles on a downward march
             const int sb = m & 3, sc0 = (m + 1) & 3, sa = (m + 2) & 3;
             A S[2][3];
-            force_sum<A, FP>(psiS[dz > 0 ? sb : sa], psiS[sc0], psiS[dz > 0 ? sa : sb], sc, sr, row, S);
-            collide_node<A>(I, v, S, psiS[sc0][0][fo], psiS[sc0][1][fo]);
+            force_sum<A>(psiS[dz > 0 ? sb : sa], psiS[sc0], psiS[dz > 0 ? sa : sb], sc, sr, row, S);
+            const Psi2<A> pc = psiS[sc0].get(fo);
+            collide_node<A>(I, v, S, pc[0], pc[1]);
         }
         store_node<St>(d, I, z, xy, v);
     };
