@@ -280,15 +280,28 @@ __device__ __forceinline__ void bstore2(_Float16 a, _Float16 b, Rsrc r, uint32_t
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)voff, (int)soff, kStorePolicy);
 }
 
+// One (A, B) pair of FP16 values as loaded: one dword.
+__device__ __forceinline__ H2 bload_h2(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(H2, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+
 // Raw stored values of one pulled node, as loaded: the loads can be issued
 // well before the values are decoded. FP16N carries, per population, the
-// moving value h_i and the FP32 rest deviation d_0 of its source node.
-template <class S, bool NODE = S::kNode> struct RawNode {
+// moving value h_i and the FP32 rest deviation d_0 of its source node. FP16
+// pairs stay one (A, B) dword per population: split into per-component
+// arrays, the compiler re-packed the halves of adjacent populations with a
+// permute per load.
+template <class S> constexpr bool kHalfPair = S::kPair && sizeof(typename S::T) == 2;
+template <class S, bool NODE = S::kNode, bool HP = kHalfPair<S>> struct RawNode {
     typename S::T v[2][kQ];
 };
-template <class S> struct RawNode<S, true> {
+template <class S> struct RawNode<S, false, true> {
+    H2 v2[kQ];
+};
+template <class S> struct RawNode<S, true, true> {
     float d0[2][kQ];
-    typename S::T h[2][kQ];
+    H2 h2[kQ];
 };
 
 // Source of each population of the pull of node (x, y, z): population i
@@ -366,12 +379,12 @@ __device__ __forceinline__ void pull_raw(const typename S::T* __restrict__ src, 
             const Pair<float> d = bload2<float>(a.rsrc(i), a.xy(i) * pair_bytes<S>(0), pair_off<S>(0, a.ps));
             w.d0[0][i] = d.a;
             w.d0[1][i] = d.b;
-            if (i != 0) {
-                const Pair<T> h = bload2<T>(a.rsrc(i), a.xy(i) * pair_bytes<S>(i), pair_off<S>(a.q(i), a.ps));
-                w.h[0][i] = h.a;
-                w.h[1][i] = h.b;
-            }
+            if (i != 0) w.h2[i] = bload_h2(a.rsrc(i), a.xy(i) * pair_bytes<S>(i), pair_off<S>(a.q(i), a.ps));
         }
+    } else if constexpr (kHalfPair<S>) {
+        const PullAddr<S> a(src, I, x, y, z);
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) w.v2[i] = bload_h2(a.rsrc(i), a.xy(i) * pair_bytes<S>(i), pair_off<S>(a.q(i), a.ps));
     } else {
         pull_vals<S>(src, I, x, y, z, w.v);
     }
@@ -380,7 +393,7 @@ __device__ __forceinline__ void pull_raw(const typename S::T* __restrict__ src, 
 // FP16N moving values alone: the pipelined step takes the rest values of the
 // source nodes from an LDS ring rather than with 19 loads per node.
 template <class S> struct RawH {
-    typename S::T h[2][kQ];
+    H2 h2[kQ];
 };
 
 // Issues the loads of the moving values of the pull of node (x, y, z).
@@ -392,11 +405,7 @@ __device__ __forceinline__ void pull_h(const typename S::T* __restrict__ src, co
     static_assert(S::kNode, "per-node rest encodings only");
     const PullAddr<S> a(src, I, x, y, z);
 #pragma unroll
-    for (int i = 1; i < kQ; ++i) {
-        const Pair<T> h = bload2<T>(a.rsrc(i), a.xy(i) * pair_bytes<S>(i), pair_off<S>(a.q(i), a.ps));
-        w.h[0][i] = h.a;
-        w.h[1][i] = h.b;
-    }
+    for (int i = 1; i < kQ; ++i) w.h2[i] = bload_h2(a.rsrc(i), a.xy(i) * pair_bytes<S>(i), pair_off<S>(a.q(i), a.ps));
 }
 
 // Decodes the raw values into deviations f_i - w_i rho0.
@@ -409,7 +418,9 @@ __device__ __forceinline__ void decode_raw(const RawNode<S>& w, NodeVals<A>& v)
         for (int c = 0; c < 2; ++c) {
             if constexpr (S::kNode) {
                 // d_i = k_i d_0(source) + h_i(source)
-                v.f[c][i] = i == 0 ? w.d0[c][0] : kRatio(i) * w.d0[c][i] + (float)w.h[c][i];
+                v.f[c][i] = i == 0 ? w.d0[c][0] : kRatio(i) * w.d0[c][i] + (float)w.h2[i][c];
+            } else if constexpr (kHalfPair<S>) {
+                v.f[c][i] = (A)w.v2[i][c];
             } else {
                 v.f[c][i] = (A)w.v[c][i];
             }
@@ -1109,7 +1120,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<S
                                               : restS[(me - dz * e + 2) & 3][(int)b - ey(i) * W - ex(i)];
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
-                    v.f[c][i] = i == 0 ? d[c] : kRatio(i) * d[c] + (float)w.h[c][i];
+                    v.f[c][i] = i == 0 ? d[c] : kRatio(i) * d[c] + (float)w.h2[i][c];
             }
         };
         RawH<St> ro, rr;
