@@ -257,7 +257,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 (multi-GPU sharding is a design "
+        print("bench.py: the library steps one GPU; --gpus must be 1 (multi-GPU sharding is a design "
               "note, not implemented)", file=sys.stderr)
         sys.exit(2)
 
