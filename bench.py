@@ -247,7 +247,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20000, help="timed steps of the headline workload")
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--diag-every", type=int, default=100)
-    ap.add_argument("--forms", default="fp64,fp16s,fp16n,batched,large",
+    ap.add_argument("--forms", default="fp64,fp16s,fp16n,batched,large,film",
                     help="extra forms besides the fp32s headline (comma list, or 'none')")
     ap.add_argument("--graph", type=int, default=0, help="steps per HIP graph (0: direct launches)")
     ap.add_argument("--tiles", default="",
@@ -311,6 +311,20 @@ def main():
         del rho
         extra["large"] = big
         print(f"# large {big['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    if "film" in forms:
+        # the film configurations: 64x64x512 (FP32S and FP64) and 4x4x128
+        # (FP64, its full 1000 steps); walled, sink on the top plane
+        films = {}
+        for wl, prec, steps in ((li.film_deep(), "fp32s", max(args.steps // 10, 10)),
+                                (li.film_deep(), "fp64", max(args.steps // 10, 10)),
+                                (li.film_small(), "fp64", li.film_small().steps)):
+            r, rho = form_single(lb, torch, wl, prec, steps, 20, args.diag_every, args.graph,
+                                 min(args.tune_steps, 5))
+            del rho
+            films[f"{wl.name}_{prec}"] = r
+            print(f"# film {wl.name} {prec} {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        extra["films"] = films
         torch.cuda.empty_cache()
     ceiling = copy_ceiling(lb, torch)
 
