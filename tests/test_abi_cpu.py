@@ -145,3 +145,15 @@ def test_default_tiles_split_evenly(lib):
     # the keep step asks for 8 rows
     assert items((100, 11, 16), "fp16n", (512, 0, 0, 0, 1)) == 2 * 2    # 50 x 10 (full width: 5 rows, 3 tiles)
     assert items((100, 11, 16), "fp16n") == 3                           # pipelined: full width, 5 rows
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py steps one GPU: --gpus above 1 exits with status 2 and says
+    so, before touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "--gpus must be 1" in r.stderr
