@@ -175,7 +175,8 @@ lbsc_status lbsc_set_tiles(lbsc_ctx* ctx, const lbsc_tiles* tiles);
  * resolved nt and kernel variant. */
 lbsc_status lbsc_get_tiles(const lbsc_ctx* ctx, lbsc_tiles* out);
 /* Times candidate tile schedules (variants x nt x tile widths x chunk
- * lengths) for `steps` steps each (steps >= 2), re-times the three fastest
+ * lengths; chunks of 1, 2 and 4 planes only for contexts of fewer than 2^22
+ * nodes) for `steps` steps each (steps >= 2), re-times the three fastest
  * over three times as many steps, and keeps the best; writes it to *chosen
  * if non-NULL.
  * The populations advance during tuning (every schedule gives the same

@@ -704,13 +704,20 @@ lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
     if (s) return s;
     if (steps < 2) return fail(c, LBSC_E_ARG, "tune: steps must be >= 2");
     std::vector<lbsc_tiles> cands;
+    // Chunks of 1-4 planes are timed only on lattices below 2^22 nodes, where
+    // 16-plane chunks of 512-node tiles give fewer than two blocks per CU and
+    // each block's march is bound by its serial per-plane latency.
+    int64_t total_nodes = 0;
+    for (const auto& I : c->inst) total_nodes += I.n;
+    std::vector<int> chunks = {0, 8, 16, 32, 64};
+    if (total_nodes < (int64_t(1) << 22)) chunks.insert(chunks.end(), {1, 2, 4});
     for (int variant : {1, 2, 3})
         for (int nt : {256, 512}) {
             if (nt == 512 && c->precision == LBSC_FP64 && variant == 1) continue;  // exceeds the register file
             if (variant == 3 && c->precision == LBSC_FP64 && nt != 256)
                 continue;
             for (int tw : {0, 32, 64, 128})
-                for (int nzc : {0, 8, 16, 32, 64}) cands.push_back(lbsc_tiles{nt, tw, 0, nzc, variant});
+                for (int nzc : chunks) cands.push_back(lbsc_tiles{nt, tw, 0, nzc, variant});
         }
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
