@@ -21,6 +21,7 @@ using lbsc::Item;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kCUs = 256;  // compute units of an MI355X
 constexpr uint64_t kMagic = 0x4C4253432D434B31ull;  // "LBSC-CK1"
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -163,8 +164,10 @@ void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int mi
     // nt / min_rows); as many rows as the block holds, split evenly so that
     // no block runs a thin ragged tile; about target_items blocks per context
     // with at least 16 planes per z chunk (each chunk re-derives the
-    // densities of two extra planes). Explicit tw / th / nzc give fixed sizes
-    // with a ragged last tile.
+    // densities of two extra planes), shorter only where 16-plane chunks
+    // would leave the instance fewer blocks than its share of the CUs (a
+    // block's march is latency-bound plane by plane). Explicit tw / th / nzc
+    // give fixed sizes with a ragged last tile.
     const int full = std::max(1, nt / min_rows);
     const int cap = std::min(128, full);
     std::vector<int> xb, yb, zb;
@@ -187,9 +190,10 @@ void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int mi
     if (t.nzc > 0) {
         zb = split_range(I.nz, std::min(t.nzc, I.nz), 0);
     } else {
-        double want = (double)target_items * (double)I.n / (double)total_nodes / cols;
-        int chunks = std::max(1, (int)std::ceil(want));
-        chunks = std::min(chunks, std::max(1, I.nz / 16));
+        const double share = (double)I.n / (double)total_nodes / cols;
+        const int want = std::max(1, (int)std::ceil(target_items * share));
+        const int fill = (int)std::ceil(kCUs * share);
+        const int chunks = std::min({want, std::max({1, I.nz / 16, fill}), I.nz});
         zb = split_range(I.nz, 0, chunks);
     }
     // Order: groups of about cols/8 neighbouring tiles, each with all its z

@@ -121,7 +121,9 @@ def test_default_tiles_split_evenly(lib):
     one: a 156^3 box gets full-width tiles of 3 rows (52 tiles; 156 = 3 x 52)
     in 9 chunks, a 300-wide box three 100-wide tiles of 5 rows; the 128^3
     droplet gets 32 tiles of 128 x 4 in 8 chunks of 16 planes (FP64, 256
-    threads: 64 tiles of 64 x 4 in 4 chunks)."""
+    threads: 64 tiles of 64 x 4 in 4 chunks). Chunks shorter than 16 planes
+    are made only until the blocks number the 256 CUs: 11 chunks of the
+    32-plane box's 24 tiles, one-plane chunks of the 4x4x128 film."""
     from paper_1701_03637_amd import lbsc
 
     def items(n, prec, tiles=None):
@@ -136,15 +138,18 @@ def test_default_tiles_split_evenly(lib):
         return v.value
 
     assert items((156, 156, 156), "fp32s") == 52 * 9
-    assert items((300, 40, 32), "fp32s") == 3 * 8 * 2
+    assert items((300, 40, 32), "fp32s") == 3 * 8 * 11                  # ceil(256 / 24) chunks
     assert items((128, 128, 128), "fp32s") == 32 * 8
     assert items((128, 128, 128), "fp64") == 64 * 4
-    # cases where full-width tiles would be too thin
-    assert items((200, 9, 16), "fp32s") == 2 * 2     # 100 x 5 (full width: 2 rows, 5 tiles)
-    assert items((100, 9, 16), "fp64") == 2 * 2      # 50 x 5 (full width: 2 rows, 5 tiles)
+    assert items((4, 4, 128), "fp64") == 128
+    assert items((4, 4, 128), "fp32s") == 128
+    assert items((4, 4, 128), "fp64", (256, 0, 0, 16, 3)) == 8         # explicit chunk length
+    # cases where full-width tiles would be too thin (one-plane chunks)
+    assert items((200, 9, 16), "fp32s") == 2 * 2 * 16   # 100 x 5 (full width: 2 rows, 5 tiles)
+    assert items((100, 9, 16), "fp64") == 2 * 2 * 16    # 50 x 5 (full width: 2 rows, 5 tiles)
     # the keep step asks for 8 rows
-    assert items((100, 11, 16), "fp16n", (512, 0, 0, 0, 1)) == 2 * 2    # 50 x 10 (full width: 5 rows, 3 tiles)
-    assert items((100, 11, 16), "fp16n") == 3                           # pipelined: full width, 5 rows
+    assert items((100, 11, 16), "fp16n", (512, 0, 0, 0, 1)) == 2 * 2 * 16   # 50 x 10 (full width: 5 rows, 3 tiles)
+    assert items((100, 11, 16), "fp16n") == 3 * 16                           # pipelined: full width, 5 rows
 
 
 def test_bench_refuses_more_than_one_gpu():
