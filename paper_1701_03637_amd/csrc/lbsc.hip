@@ -1105,7 +1105,8 @@ int32_t lbsc_selftest(void)
             }
     }
     // Work items tile every lattice exactly once.
-    const int dims[][3] = {{4, 4, 128}, {128, 128, 128}, {48, 48, 48}, {156, 156, 156}, {1, 1, 64}, {200, 7, 9}};
+    const int dims[][3] = {{4, 4, 128}, {128, 128, 128}, {48, 48, 48}, {156, 156, 156}, {1, 1, 64}, {200, 7, 9},
+                           {4096, 2, 3}, {3, 4096, 2}, {2, 3, 4096}, {1, 1, 4096}};
     for (auto& d : dims)
         for (int nt : {256, 512})
             for (int tw : {0, 8, 16, 32, 64, 128, 200, 256})

@@ -79,6 +79,32 @@ def test_fp64_random_populations_match_oracle(lb, case):
     assert np.allclose(dg["momentum"], do["momentum"], atol=1e-12 * tot, rtol=0)
 
 
+@pytest.mark.parametrize("dims,sink,wall_z,radius", [
+    ((4096, 2, 3), "none", False, 0.0),
+    ((3, 4096, 2), "sphere", False, 1000.0),
+    ((2, 3, 4096), "zmax", True, 0.0),
+    ((1, 1, 4096), "zmax", True, 0.0),
+])
+def test_fp64_size_limits_match_oracle(lb, dims, sink, wall_z, radius):
+    """Lattices of the largest extent (4096) along one axis and one to three
+    nodes along the others, in the default schedule: a long x or y split
+    into many tiles, thousands of short z chunks, stencils that wrap inside
+    one- and two-node extents, and a sphere whose sink splits the long axis."""
+    nx, ny, nz = dims
+    sim, orc = _pair(lb, nx, ny, nz, psi="exp", g=2.0, sink=sink, wall_z=wall_z, rho_h=0.03, sink_radius=radius)
+    f0 = li.random_populations(nx, ny, nz, seed=11, base_a=0.3, base_b=0.4, amp=0.05)
+    sim.init_from_populations(f0)
+    orc.init_from_populations(f0)
+    sim.step(4)
+    orc.step(4)
+    _cmp_pops(sim, orc, 1e-12)
+    dg, do = sim.diagnostics(), orc.diagnostics()
+    tot = do["mass"][0] + do["mass"][1]
+    for c in range(2):
+        assert abs(dg["mass"][c] - do["mass"][c]) <= 1e-13 * tot
+    assert abs(dg["evaporated"] - do["evaporated"]) <= 1e-13 * tot
+
+
 def test_fp64_film_config_full_run(lb):
     """4x4x128 film, psi = rho, g = 0.9, sink on z = 127, wall, 1000 steps."""
     w = li.film_small()
@@ -168,6 +194,9 @@ PIPE_CASES = [
     ((150, 7, 9), False, "faces", (512, 0, 0, 0, 3)),
     ((200, 5, 11), True, "zmax", (512, 200, 2, 0, 3)),
     ((40, 24, 21), False, "sphere", (256, 40, 6, 4, 3), (0.8, 1.3)),
+    # extents at the 4096 limit, default tiles and chunks
+    ((4096, 2, 3), False, "none", (256, 0, 0, 0, 3)),
+    ((2, 3, 4096), True, "zmax", (512, 0, 0, 0, 3)),
 ]
 
 
