@@ -105,6 +105,43 @@ def test_fp64_size_limits_match_oracle(lb, dims, sink, wall_z, radius):
     assert abs(dg["evaporated"] - do["evaporated"]) <= 1e-13 * tot
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32s", 2e-6)])
+@pytest.mark.parametrize("dims,wall_z,sink", [((1, 1, 1), False, "none"), ((1, 1, 1), True, "none"),
+                                              ((1, 1, 2), True, "zmax"), ((2, 1, 1), False, "none")])
+def test_smallest_lattices_match_oracle(lb, precision, tol, dims, wall_z, sink):
+    """Degenerate lattices: every neighbour of a 1x1x1 node is the node itself
+    (periodic), or, walled, both z directions reflect off the same plane; a
+    walled 1x1x2 column whose top plane is the sink."""
+    nx, ny, nz = dims
+    sim, orc = _pair(lb, nx, ny, nz, precision=precision, psi="exp", g=2.0, sink=sink, wall_z=wall_z, rho_h=0.03)
+    f0 = li.random_populations(nx, ny, nz, seed=13, base_a=0.3, base_b=0.4, amp=0.05)
+    sim.init_from_populations(f0)
+    orc.init_from_populations(f0)
+    sim.step(6)
+    orc.step(6)
+    _cmp_pops(sim, orc, tol)
+    dg, do = sim.diagnostics(), orc.diagnostics()
+    tot = do["mass"][0] + do["mass"][1]
+    assert abs(dg["mass"][0] + dg["mass"][1] - tot) <= 10 * tol * tot
+
+
+def test_zero_and_negative_step_counts(lb):
+    """step(0) launches nothing and leaves state and step counter as they
+    are; a negative count is an argument error that changes nothing."""
+    nx, ny, nz = 12, 10, 8
+    sim = lb.Sim(lb.make_params(nx, ny, nz, psi="exp", g=2.0, sink="faces", rho_h=0.03, precision="fp32s"))
+    sim.init_from_populations(li.random_populations(nx, ny, nz, seed=2, base_a=0.3, base_b=0.4, amp=0.05))
+    sim.step(3)
+    before = sim.populations().clone()
+    sim.step(0)
+    assert torch.equal(sim.populations(), before)
+    assert sim.diagnostics()["step"] == 3
+    with pytest.raises(lb.LbscError, match="negative"):
+        sim.step(-1)
+    assert torch.equal(sim.populations(), before)
+    assert sim.diagnostics()["step"] == 3
+
+
 def test_fp64_film_config_full_run(lb):
     """4x4x128 film, psi = rho, g = 0.9, sink on z = 127, wall, 1000 steps."""
     w = li.film_small()
