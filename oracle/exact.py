@@ -133,3 +133,25 @@ class ExactLattice:
                     new[c][n][e] = v
         self.f = new
         self._reset(count=True)
+
+    def velocity(self):
+        """Barycentric velocity U of Eq. (velw) at every node of the state:
+        U = (sum_c j^c + (F^A + F^B)/2) / (rho^A + rho^B), with the force of
+        Eq. (sc) from the state's own densities; sink nodes feel no force
+        (Sec. II C). Returns {node: (Ux, Uy, Uz)}."""
+        rho = [{n: self.density(c, n) for n in self.nodes} for c in range(2)]
+        ps = [{n: psi(rho[c][n], self.psi_kind) for n in self.nodes} for c in range(2)]
+        out = {}
+        for n in self.nodes:
+            num = [sum(self.f[c][n][e] * e[d] for c in range(2) for e in VELOCITIES) for d in range(3)]
+            if not self.is_sink(n):
+                for c in range(2):
+                    for e in VELOCITIES:
+                        if e == (0, 0, 0):
+                            continue
+                        pn = ps[1 - c][self._neighbour_for_psi(n, e)]
+                        for d in range(3):
+                            num[d] += -ps[c][n] * self.g * weight(e) * pn * e[d] / 2
+            rt = rho[0][n] + rho[1][n]
+            out[n] = tuple(num[d] / rt for d in range(3))
+        return out

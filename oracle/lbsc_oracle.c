@@ -89,6 +89,7 @@ typedef struct {
     double *fs;       /* post-collision populations f* */
     double *rho;      /* rho[c*n + node] */
     double *psi;      /* psi[c*n + node] */
+    double *flux;     /* per-node sink flux of the last reset (NaN: no sink node) */
     double evaporated;
     double evap_rate;
     long long step;
@@ -152,10 +153,13 @@ static long long node_index(const orc_lattice *L, int x, int y, int z)
     return ((long long)z * L->p.ny + y) * L->p.nx + x;
 }
 
+/* Periodic wrap of a coordinate one step outside [0, n) (every caller steps
+ * by at most one node). */
 static int wrap(int a, int n)
 {
-    a %= n;
-    return a < 0 ? a + n : a;
+    if (a < 0) return a + n;
+    if (a >= n) return a - n;
+    return a;
 }
 
 static int is_sink(const orc_params *p, int x, int y, int z)
@@ -187,8 +191,9 @@ orc_lattice *orc_create(const orc_params *p)
     L->fs = (double *)calloc((size_t)(2 * NQ * L->n), sizeof(double));
     L->rho = (double *)calloc((size_t)(2 * L->n), sizeof(double));
     L->psi = (double *)calloc((size_t)(2 * L->n), sizeof(double));
-    if (!L->f || !L->fs || !L->rho || !L->psi) {
-        free(L->f); free(L->fs); free(L->rho); free(L->psi); free(L);
+    L->flux = (double *)calloc((size_t)L->n, sizeof(double));
+    if (!L->f || !L->fs || !L->rho || !L->psi || !L->flux) {
+        free(L->f); free(L->fs); free(L->rho); free(L->psi); free(L->flux); free(L);
         return NULL;
     }
     return L;
@@ -197,25 +202,29 @@ orc_lattice *orc_create(const orc_params *p)
 void orc_destroy(orc_lattice *L)
 {
     if (!L) return;
-    free(L->f); free(L->fs); free(L->rho); free(L->psi);
+    free(L->f); free(L->fs); free(L->rho); free(L->psi); free(L->flux);
     free(L);
 }
 
 /* ---- the sink (Sec. II C) ------------------------------------------------ */
 
 /* Resets every sink node of the post-stream state in L->f and returns
- * sum over sink nodes of (rhoA_pre - rho_H), summed in node order. */
+ * sum over sink nodes of (rhoA_pre - rho_H), summed serially in node order.
+ * The per-node resets are independent and run in parallel; each node's
+ * flux is kept in L->flux (NaN at nodes outside the sink) for the sum. */
 static double apply_sink(orc_lattice *L)
 {
     const orc_params *p = &L->p;
     const long long n = L->n;
     double flux = 0.0;
     if (p->sink_kind == ORC_SINK_NONE) return 0.0;
+#pragma omp parallel for schedule(static)
     for (int z = 0; z < p->nz; ++z)
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
-                if (!is_sink(p, x, y, z)) continue;
                 long long k = node_index(L, x, y, z);
+                L->flux[k] = NAN;
+                if (!is_sink(p, x, y, z)) continue;
                 double ra = 0.0, rb = 0.0;
                 for (int i = 0; i < NQ; ++i) {
                     ra += L->f[(0 * NQ + i) * n + k];
@@ -226,8 +235,10 @@ static double apply_sink(orc_lattice *L)
                     L->f[(0 * NQ + i) * n + k] = feq(i, p->rho_h, 0.0, 0.0, 0.0);
                     L->f[(1 * NQ + i) * n + k] = feq(i, rb_h, 0.0, 0.0, 0.0);
                 }
-                flux += ra - p->rho_h;
+                L->flux[k] = ra - p->rho_h;
             }
+    for (long long k = 0; k < n; ++k)
+        if (!isnan(L->flux[k])) flux += L->flux[k];
     return flux;
 }
 
@@ -356,22 +367,24 @@ static void collide(orc_lattice *L)
             }
 }
 
+/* Pull streaming, one (component, direction) plane at a time. */
 static void stream(orc_lattice *L)
 {
     const orc_params *p = &L->p;
     const long long n = L->n;
+    for (int c = 0; c < 2; ++c)
+        for (int i = 0; i < NQ; ++i) {
+            const int io = opposite(i);
 #pragma omp parallel for schedule(static)
-    for (int z = 0; z < p->nz; ++z)
-        for (int y = 0; y < p->ny; ++y)
-            for (int x = 0; x < p->nx; ++x) {
-                long long k = node_index(L, x, y, z);
-                for (int i = 0; i < NQ; ++i) {
-                    int zs = z - EZ[i];
-                    int across_wall = p->wall_z && (zs < 0 || zs >= p->nz);
-                    for (int c = 0; c < 2; ++c) {
+            for (int z = 0; z < p->nz; ++z) {
+                int zs = z - EZ[i];
+                int across_wall = p->wall_z && (zs < 0 || zs >= p->nz);
+                for (int y = 0; y < p->ny; ++y)
+                    for (int x = 0; x < p->nx; ++x) {
+                        long long k = node_index(L, x, y, z);
                         double v;
                         if (across_wall) {
-                            v = L->fs[(c * NQ + opposite(i)) * n + k];
+                            v = L->fs[(c * NQ + io) * n + k];
                         } else {
                             long long ks = node_index(L, wrap(x - EX[i], p->nx), wrap(y - EY[i], p->ny),
                                                       wrap(zs, p->nz));
@@ -379,8 +392,8 @@ static void stream(orc_lattice *L)
                         }
                         L->f[(c * NQ + i) * n + k] = v;
                     }
-                }
             }
+        }
 }
 
 void orc_step(orc_lattice *L, long long nsteps)

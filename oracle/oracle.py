@@ -29,7 +29,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (OpenMP over independent per-node loops)."""
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp"
-        cmd = ["gcc", "-std=gnu11", "-O2", "-fPIC", "-shared", "-fopenmp", "-o", tmp, _SRC, "-lm"]
+        cmd = ["gcc", "-std=gnu11", "-O3", "-fPIC", "-shared", "-fopenmp", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
