@@ -7,7 +7,9 @@ digits (mpmath), so FP64 rounding and summation order play no part. It follows t
 as the C oracle: moments and common velocity (Sec. II A), the Shan-Chen force
 (Eq. (sc)), the force shift (Sec. II B), BGK towards Eq. (eqdis), pull
 streaming with periodic wrap or a bounce-back wall at the z seam, and the
-mass-conserving sink (Sec. II C).
+mass-conserving sink (Sec. II C). Solid wall nodes (Sec. III A, III B) hold
+no fluid, reflect every population a fluid neighbour would pull from them,
+and carry psi of given wall densities in the force.
 """
 from __future__ import annotations
 
@@ -43,24 +45,35 @@ class ExactLattice:
 
     Parameters given as strings or integers are converted exactly."""
 
-    def __init__(self, nx, ny, nz, g, tau=(1, 1), psi_kind="rho", wall_z=False, sink=None, rho_h=0):
+    def __init__(self, nx, ny, nz, g, tau=(1, 1), psi_kind="rho", wall_z=False, sink=None, rho_h=0, solid=None,
+                 wall_rho=(0, 0)):
         self.dims = (nx, ny, nz)
         self.g = mpf(g)
         self.tau = (mpf(tau[0]), mpf(tau[1]))
         self.psi_kind = psi_kind
         self.wall_z = wall_z
         self.sink = sink  # callable (x, y, z) -> bool, or None
+        self.solid = solid  # callable (x, y, z) -> bool, or None
+        self.wall_rho = (mpf(wall_rho[0]), mpf(wall_rho[1]))
         self.rho_h = mpf(rho_h)
         self.evaporated = mpf(0)
         self.nodes = [(x, y, z) for z in range(nz) for y in range(ny) for x in range(nx)]
         self.f = [dict(), dict()]
 
     def is_sink(self, node):
-        return self.sink is not None and self.sink(*node)
+        return self.sink is not None and self.sink(*node) and not self.is_solid(node)
+
+    def is_solid(self, node):
+        return self.solid is not None and self.solid(*node)
+
+    def _psi_field(self, rho):
+        return [{n: psi(self.wall_rho[c] if self.is_solid(n) else rho[c][n], self.psi_kind) for n in self.nodes}
+                for c in range(2)]
 
     def set_populations(self, pops):
         """pops[c][node][e] -> number; then the uncounted sink reset."""
-        self.f = [{n: {e: mpf(v) for e, v in pops[c][n].items()} for n in self.nodes} for c in range(2)]
+        self.f = [{n: {e: (mpf(0) if self.is_solid(n) else mpf(v)) for e, v in pops[c][n].items()}
+                   for n in self.nodes} for c in range(2)]
         self._reset(count=False)
 
     def density(self, c, node):
@@ -91,9 +104,13 @@ class ExactLattice:
     def step(self):
         nx, ny, nz = self.dims
         rho = [{n: self.density(c, n) for n in self.nodes} for c in range(2)]
-        ps = [{n: psi(rho[c][n], self.psi_kind) for n in self.nodes} for c in range(2)]
+        ps = self._psi_field(rho)
         post = [dict(), dict()]
         for n in self.nodes:
+            if self.is_solid(n):
+                post[0][n] = {e: mpf(0) for e in VELOCITIES}
+                post[1][n] = {e: mpf(0) for e in VELOCITIES}
+                continue
             if self.is_sink(n):
                 post[0][n] = dict(self.f[0][n])
                 post[1][n] = dict(self.f[1][n])
@@ -125,11 +142,14 @@ class ExactLattice:
                 new[c].setdefault(n, {})
             for e in VELOCITIES:
                 zs = z - e[2]
+                src = ((x - e[0]) % nx, (y - e[1]) % ny, zs % nz)
                 for c in range(2):
-                    if self.wall_z and (zs < 0 or zs >= nz):
+                    if self.is_solid(n):
+                        v = mpf(0)
+                    elif (self.wall_z and (zs < 0 or zs >= nz)) or self.is_solid(src):
                         v = post[c][n][(-e[0], -e[1], -e[2])]
                     else:
-                        v = post[c][((x - e[0]) % nx, (y - e[1]) % ny, zs % nz)][e]
+                        v = post[c][src][e]
                     new[c][n][e] = v
         self.f = new
         self._reset(count=True)
@@ -140,9 +160,12 @@ class ExactLattice:
         Eq. (sc) from the state's own densities; sink nodes feel no force
         (Sec. II C). Returns {node: (Ux, Uy, Uz)}."""
         rho = [{n: self.density(c, n) for n in self.nodes} for c in range(2)]
-        ps = [{n: psi(rho[c][n], self.psi_kind) for n in self.nodes} for c in range(2)]
+        ps = self._psi_field(rho)
         out = {}
         for n in self.nodes:
+            if self.is_solid(n):
+                out[n] = (mpf(0), mpf(0), mpf(0))
+                continue
             num = [sum(self.f[c][n][e] * e[d] for c in range(2) for e in VELOCITIES) for d in range(3)]
             if not self.is_sink(n):
                 for c in range(2):

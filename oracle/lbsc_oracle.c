@@ -32,8 +32,13 @@
  * the design notes of the repository):
  *   - direction order: 0 rest, 1-6 = +-x, +-y, +-z, 7-18 the twelve face
  *     diagonals with opposites adjacent (the paper fixes only the weights);
- *   - the wall mirrors psi across the seam (psi(z=-1) := psi(z=0)), so a wall
- *     next to a uniform fluid exerts no force (neutral wetting);
+ *   - the seam wall mirrors psi across the seam (psi(z=-1) := psi(z=0)), so
+ *     a wall next to a uniform fluid exerts no force (neutral wetting);
+ *   - a solid wall (Sec. III A, III B: "a wall of thickness 2 with simple
+ *     bounce back") is a layer of solid nodes: every population a fluid node
+ *     would pull from a solid node is its own reflected one (half-way
+ *     bounce-back); solid nodes hold no fluid and enter the force of Eq. (sc)
+ *     with psi of given wall densities (0: no interaction with the wall);
  *   - at rho^c = 0 the force shift is taken as zero (f^eq is then zero for
  *     any finite velocity);
  *   - a sink switched on mid-run is skipped by the next collision and resets
@@ -68,6 +73,8 @@ typedef struct {
     double sink_radius;
     double center[3];
     double phi_delta[2]; /* (rhoA - rhoB) inside / outside a droplet */
+    int solid_z;       /* solid wall nodes at z = 0 .. solid_z - 1 (0: none) */
+    double wall_rho[2];  /* densities whose psi the solid nodes carry */
 } orc_params;
 
 typedef struct {
@@ -178,11 +185,15 @@ static int is_sink(const orc_params *p, int x, int y, int z)
     }
 }
 
+/* Solid wall node (the layer z < solid_z). */
+static int is_solid(const orc_params *p, int z) { return z < p->solid_z; }
+
 /* ---- lifecycle ----------------------------------------------------------- */
 
 orc_lattice *orc_create(const orc_params *p)
 {
     if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0) return NULL;
+    if (p->solid_z < 0 || p->solid_z >= p->nz || (p->solid_z > 0 && p->wall_z)) return NULL;
     orc_lattice *L = (orc_lattice *)calloc(1, sizeof(orc_lattice));
     if (!L) return NULL;
     L->p = *p;
@@ -224,7 +235,7 @@ static double apply_sink(orc_lattice *L)
             for (int x = 0; x < p->nx; ++x) {
                 long long k = node_index(L, x, y, z);
                 L->flux[k] = NAN;
-                if (!is_sink(p, x, y, z)) continue;
+                if (!is_sink(p, x, y, z) || is_solid(p, z)) continue;
                 double ra = 0.0, rb = 0.0;
                 for (int i = 0; i < NQ; ++i) {
                     ra += L->f[(0 * NQ + i) * n + k];
@@ -244,6 +255,14 @@ static double apply_sink(orc_lattice *L)
 
 /* ---- initialisation ------------------------------------------------------ */
 
+/* Solid nodes hold no fluid: their populations are zero. */
+static void clear_solid(orc_lattice *L)
+{
+    const long long n = L->n, plane = (long long)L->p.nx * L->p.ny;
+    for (int q = 0; q < 2 * NQ; ++q)
+        for (long long k = 0; k < (long long)L->p.solid_z * plane; ++k) L->f[q * n + k] = 0.0;
+}
+
 /* f = f^eq(rho, 0) at every node, then the initial sink reset, which is not
  * counted as evaporated mass. */
 void orc_init_from_density(orc_lattice *L, const double *rhoA, const double *rhoB)
@@ -254,6 +273,7 @@ void orc_init_from_density(orc_lattice *L, const double *rhoA, const double *rho
             L->f[(0 * NQ + i) * n + k] = feq(i, rhoA[k], 0.0, 0.0, 0.0);
             L->f[(1 * NQ + i) * n + k] = feq(i, rhoB[k], 0.0, 0.0, 0.0);
         }
+    clear_solid(L);
     L->evap_rate = apply_sink(L);
     L->evaporated = 0.0;
     L->step = 0;
@@ -263,6 +283,7 @@ void orc_init_from_density(orc_lattice *L, const double *rhoA, const double *rho
 void orc_init_from_populations(orc_lattice *L, const double *f)
 {
     memcpy(L->f, f, sizeof(double) * (size_t)(2 * NQ * L->n));
+    clear_solid(L);
     L->evap_rate = apply_sink(L);
     L->evaporated = 0.0;
     L->step = 0;
@@ -277,16 +298,17 @@ void orc_set_sink(orc_lattice *L, int kind, double rho_h, double radius)
 
 /* ---- moments and force --------------------------------------------------- */
 
+/* Densities and psi at every node; solid nodes carry psi(wall_rho[c]). */
 static void compute_density_psi(orc_lattice *L)
 {
-    const long long n = L->n;
+    const long long n = L->n, solid_end = (long long)L->p.solid_z * L->p.nx * L->p.ny;
 #pragma omp parallel for schedule(static)
     for (long long k = 0; k < n; ++k)
         for (int c = 0; c < 2; ++c) {
             double r = 0.0;
             for (int i = 0; i < NQ; ++i) r += L->f[(c * NQ + i) * n + k];
             L->rho[c * n + k] = r;
-            L->psi[c * n + k] = psi_of(&L->p, r);
+            L->psi[c * n + k] = k < solid_end ? psi_of(&L->p, L->p.wall_rho[c]) : psi_of(&L->p, r);
         }
 }
 
@@ -340,6 +362,10 @@ static void collide(orc_lattice *L)
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
                 long long k = node_index(L, x, y, z);
+                if (is_solid(p, z)) {
+                    for (int q = 0; q < 2 * NQ; ++q) L->fs[q * n + k] = 0.0;
+                    continue;
+                }
                 if (is_sink(p, x, y, z)) {
                     for (int q = 0; q < 2 * NQ; ++q) L->fs[q * n + k] = L->f[q * n + k];
                     continue;
@@ -367,7 +393,9 @@ static void collide(orc_lattice *L)
             }
 }
 
-/* Pull streaming, one (component, direction) plane at a time. */
+/* Pull streaming, one (component, direction) plane at a time. A population
+ * that would come across the seam wall or out of a solid node is the node's
+ * own reflected one; solid nodes stay empty. */
 static void stream(orc_lattice *L)
 {
     const orc_params *p = &L->p;
@@ -379,11 +407,14 @@ static void stream(orc_lattice *L)
             for (int z = 0; z < p->nz; ++z) {
                 int zs = z - EZ[i];
                 int across_wall = p->wall_z && (zs < 0 || zs >= p->nz);
+                int from_solid = !p->wall_z && is_solid(p, wrap(zs, p->nz));
                 for (int y = 0; y < p->ny; ++y)
                     for (int x = 0; x < p->nx; ++x) {
                         long long k = node_index(L, x, y, z);
                         double v;
-                        if (across_wall) {
+                        if (is_solid(p, z)) {
+                            v = 0.0;
+                        } else if (across_wall || from_solid) {
                             v = L->fs[(c * NQ + io) * n + k];
                         } else {
                             long long ks = node_index(L, wrap(x - EX[i], p->nx), wrap(y - EY[i], p->ny),
@@ -425,7 +456,7 @@ void orc_get_density(orc_lattice *L, double *rhoA, double *rhoB)
 
 /* Barycentric velocity U of Eq. (velw):
  * U = (sum_c rho^c u^c + (F^A + F^B)/2) / (rho^A + rho^B); no force acts at
- * sink nodes.  out3[d*n + node]. */
+ * sink nodes; solid nodes have U = 0.  out3[d*n + node]. */
 void orc_get_velocity(orc_lattice *L, double *out3)
 {
     const orc_params *p = &L->p;
@@ -436,6 +467,10 @@ void orc_get_velocity(orc_lattice *L, double *out3)
             for (int x = 0; x < p->nx; ++x) {
                 long long k = node_index(L, x, y, z);
                 double num[3] = {0.0, 0.0, 0.0};
+                if (is_solid(p, z)) {
+                    for (int d = 0; d < 3; ++d) out3[d * n + k] = 0.0;
+                    continue;
+                }
                 for (int c = 0; c < 2; ++c) {
                     double j[3], F[3] = {0.0, 0.0, 0.0};
                     momentum_of(L, c, k, j);
@@ -447,7 +482,7 @@ void orc_get_velocity(orc_lattice *L, double *out3)
             }
 }
 
-/* Total Shan-Chen force summed over all nodes and both components. */
+/* Total Shan-Chen force summed over all fluid nodes and both components. */
 void orc_total_force(orc_lattice *L, double out[3])
 {
     const orc_params *p = &L->p;
@@ -458,12 +493,14 @@ void orc_total_force(orc_lattice *L, double out[3])
             for (int x = 0; x < p->nx; ++x)
                 for (int c = 0; c < 2; ++c) {
                     double F[3];
+                    if (is_solid(p, z)) continue;
                     sc_force(L, c, x, y, z, F);
                     for (int d = 0; d < 3; ++d) out[d] += F[d];
                 }
 }
 
-/* Mass, evaporated mass, momentum, interface height and droplet radius. */
+/* Mass, evaporated mass, momentum, interface height and droplet radius, over
+ * the fluid nodes. */
 void orc_diagnostics(orc_lattice *L, orc_diag *out)
 {
     const orc_params *p = &L->p;
@@ -479,6 +516,7 @@ void orc_diagnostics(orc_lattice *L, orc_diag *out)
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
                 long long k = node_index(L, x, y, z);
+                if (is_solid(p, z)) continue;
                 double ra = L->rho[k], rb = L->rho[n + k];
                 out->mass[0] += ra;
                 out->mass[1] += rb;
@@ -496,10 +534,10 @@ void orc_diagnostics(orc_lattice *L, orc_diag *out)
                 phisum += phi;
             }
     /* Interface: first sign change of the plane-averaged rhoA - rhoB scanning
-     * up from z = 0, located by linear interpolation. */
+     * up from the lowest fluid plane, located by linear interpolation. */
     out->z_interface = NAN;
     double area = (double)p->nx * p->ny;
-    for (int z = 0; z + 1 < p->nz; ++z) {
+    for (int z = p->solid_z; z + 1 < p->nz; ++z) {
         double a = prof[z] / area, b = prof[z + 1] / area;
         if ((a > 0.0 && b <= 0.0) || (a < 0.0 && b >= 0.0)) {
             out->z_interface = z + a / (a - b);
@@ -520,5 +558,15 @@ int orc_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Sets the threads of the per-node loops (results do not depend on it). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }

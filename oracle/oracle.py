@@ -47,6 +47,8 @@ class _Params(ctypes.Structure):
         ("sink_radius", ctypes.c_double),
         ("center", ctypes.c_double * 3),
         ("phi_delta", ctypes.c_double * 2),
+        ("solid_z", ctypes.c_int),
+        ("wall_rho", ctypes.c_double * 2),
     ]
 
 
@@ -89,6 +91,7 @@ def _load():
         lib.orc_lattice_tables.argtypes = [ip, ip, ip, dp, ip]
         lib.orc_feq.argtypes = [ctypes.c_double] * 4 + [dp]
         lib.orc_num_threads.restype = ctypes.c_int
+        lib.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = lib
         return lib
 
@@ -109,6 +112,11 @@ def lattice_tables():
 def num_threads() -> int:
     """Threads the oracle's per-node loops use."""
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int):
+    """Threads of the oracle's per-node loops (results do not depend on it)."""
+    _load().orc_set_num_threads(int(n))
 
 
 def feq(rho: float, u) -> np.ndarray:
@@ -133,6 +141,8 @@ class OracleParams:
     sink_radius: float = 0.0
     center: tuple | None = None
     phi_delta: tuple = (0.66, -0.66)
+    solid_z: int = 0
+    wall_rho: tuple = (0.0, 0.0)
 
 
 class Oracle:
@@ -145,7 +155,8 @@ class Oracle:
         self.n = p.nx * p.ny * p.nz
         c = p.center if p.center is not None else ((p.nx - 1) / 2, (p.ny - 1) / 2, (p.nz - 1) / 2)
         cp = _Params(p.nx, p.ny, p.nz, int(p.wall_z), (ctypes.c_double * 2)(*p.tau), p.g, p.psi, p.sink,
-                     p.rho_h, p.sink_radius, (ctypes.c_double * 3)(*c), (ctypes.c_double * 2)(*p.phi_delta))
+                     p.rho_h, p.sink_radius, (ctypes.c_double * 3)(*c), (ctypes.c_double * 2)(*p.phi_delta),
+                     int(p.solid_z), (ctypes.c_double * 2)(*p.wall_rho))
         self._h = lib.orc_create(ctypes.byref(cp))
         if not self._h:
             raise ValueError("oracle: invalid lattice parameters")

@@ -201,12 +201,19 @@ def _from_exact(lat, nx, ny, nz):
     return out
 
 
-@pytest.mark.parametrize("case", ["wall_zmax_rho", "periodic_exp", "unequal_tau", "sphere_rho"])
+@pytest.mark.parametrize("case", ["wall_zmax_rho", "periodic_exp", "unequal_tau", "sphere_rho", "solid_wall_exp"])
 def test_oracle_matches_exact_bruteforce(case):
     nx, ny, nz = 3, 2, 4
     kw = dict(g=0.9, psi=PSI_RHO, tau=(1.0, 1.0))
     ekw = dict(g="0.9", psi_kind="rho")
     steps = 3
+    if case == "solid_wall_exp":
+        # solid wall of thickness 2 below the fluid and, through the periodic
+        # wrap, above it; the wall carries psi(0.125), psi(0.25)
+        nz = 5
+        kw.update(g=2.0, psi=PSI_EXP, solid_z=2, wall_rho=(0.125, 0.25), sink=SINK_ZMAX, rho_h=0.03125)
+        ekw.update(g="2.0", psi_kind="exp", solid=lambda x, y, z: z < 2, wall_rho=("0.125", "0.25"),
+                   sink=lambda x, y, z: z == nz - 1, rho_h="0.03125")
     if case == "wall_zmax_rho":
         kw.update(wall_z=True, sink=SINK_ZMAX, rho_h=0.03125)
         ekw.update(wall_z=True, sink=lambda x, y, z: z == nz - 1, rho_h="0.03125")
@@ -280,6 +287,127 @@ def test_velocity_force_term_closed_form(wall):
         assert np.max(np.abs(expect + g * a * (e / 3) * np.sin(k) * np.cos(k * z) / (2 * (a + rb)))) < 1e-17
     assert np.max(np.abs(U[2] - expect[:, None, None])) < 1e-16
     assert np.max(np.abs(U[:2])) < 1e-17
+
+
+# ---------------------------------------------------------------------------
+# Solid walls of thickness 2 (Sec. III A, III B): bounce-back links out of
+# solid nodes, psi of the wall densities in the force.
+# ---------------------------------------------------------------------------
+
+def test_solid_wall_without_force_equals_seam_wall():
+    """With g = 0 the wall's psi plays no part, and a fluid above a solid
+    layer of h planes streams exactly like the same fluid between seam walls:
+    both reflect every link that leaves the fluid (half-way bounce-back)."""
+    nx, ny, n, h = 3, 2, 7, 2
+    f0 = li.random_populations(nx, ny, n, seed=31, base_a=0.3, base_b=0.4, amp=0.05)
+    seam = Oracle(_params(nx, ny, n, g=0.0, wall_z=True, sink=SINK_ZMAX, rho_h=0.03))
+    seam.init_from_populations(f0)
+    solid = Oracle(_params(nx, ny, n + h, g=0.0, solid_z=h, wall_rho=(0.5, 0.5), sink=SINK_ZMAX, rho_h=0.03))
+    fs = np.zeros((2, 19, n + h, ny, nx))
+    fs[:, :, h:] = f0
+    fs[:, :, :h] = 7.0          # anything put into the wall is cleared
+    solid.init_from_populations(fs)
+    seam.step(9)
+    solid.step(9)
+    got = solid.populations()
+    assert np.array_equal(got[:, :, h:], seam.populations())
+    assert not np.any(got[:, :, :h])
+    ds, dw = solid.diagnostics(), seam.diagnostics()
+    assert ds["mass"] == dw["mass"] and ds["evaporated"] == dw["evaporated"]
+
+
+@pytest.mark.parametrize("psi", [PSI_RHO, PSI_EXP])
+def test_solid_wall_conserves_each_mass(psi):
+    o = Oracle(_params(4, 3, 9, g=1.7, psi=psi, solid_z=2, wall_rho=(0.2, 0.6)))
+    o.init_from_populations(li.random_populations(4, 3, 9, seed=12))
+    d0 = o.diagnostics()
+    o.step(50)
+    d1 = o.diagnostics()
+    for c in range(2):
+        assert abs(d1["mass"][c] - d0["mass"][c]) <= 1e-13 * d0["mass"][c]
+
+
+@pytest.mark.parametrize("wall_rho", [(0.0, 0.0), (0.2, 0.55)])
+def test_solid_wall_force_closed_form(wall_rho):
+    """Uniform rest fluid (a, b) above a solid layer, psi = rho: at the first
+    fluid plane the neighbour sum of Eq. (sc) has S^c_z = (1/18 + 4/36)
+    (psi^c - psi^c_w) = (psi^c - psi^c_w)/6 (five links reach the wall), at
+    the top plane (next to the wall through the periodic wrap) the opposite,
+    and zero in between. U of Eq. (velw) is then
+    U_z = -g (a S^B_z + b S^A_z) / (2 (a + b)); solid nodes report U = 0."""
+    nz, h, a, b, g = 10, 2, 0.3, 0.45, 1.3
+    o = Oracle(_params(2, 2, nz, g=g, psi=PSI_RHO, solid_z=h, wall_rho=wall_rho))
+    o.init_from_density(np.full((nz, 2, 2), a), np.full((nz, 2, 2), b))
+    U = o.velocity()
+    s_a, s_b = (a - wall_rho[0]) / 6, (b - wall_rho[1]) / 6
+    uz = -g * (a * s_b + b * s_a) / (2 * (a + b))
+    expect = np.zeros(nz)
+    expect[h], expect[nz - 1] = uz, -uz
+    assert np.max(np.abs(U[2] - expect[:, None, None])) < 1e-16
+    assert np.max(np.abs(U[:2])) < 1e-17
+    ra, rb = o.density()
+    assert not np.any(ra[:h]) and not np.any(rb[:h])
+
+
+def test_solid_wall_planar_state_independent_of_cross_section():
+    a, b = li.film(1, 1, 26, 12)
+    kw = dict(g=3.6, psi=PSI_EXP, solid_z=2, wall_rho=(0.1, 0.0), sink=SINK_ZMAX, rho_h=0.02)
+    o1 = Oracle(_params(1, 1, 26, **kw))
+    o1.init_from_density(a, b); o1.step(30)
+    a3, b3 = li.film(3, 2, 26, 12)
+    o3 = Oracle(_params(3, 2, 26, **kw))
+    o3.init_from_density(a3, b3); o3.step(30)
+    assert np.max(np.abs(o3.density()[0] - o1.density()[0][:, :1, :1])) < 1e-15
+
+
+def test_film_on_a_solid_wall_matches_printed_coexistence():
+    """Sec. III B's film: 128 nodes, a solid wall of thickness 2 at the
+    bottom that does not interact (psi_w = 0, "simple bounce back"), A (0.70)
+    below the interface at 64 and B above (0.04 minority), psi = 1 -
+    exp(-rho), g = 3.6. The bulk phases reach rho_ma ~ 0.704 and rho_mi ~
+    0.036 (printed); measured 0.7092 and 0.0361. In a closed binary system
+    the bulk point moves along the coexistence curve with what the wall
+    layers adsorb: the seam wall gives 0.7080, a neutral solid wall (equal
+    wall densities 0.37) 0.7113, so no wall rule reproduces 0.704 exactly."""
+    nz = 128
+    wall_rho = (0.0, 0.0)
+    o = Oracle(_params(1, 1, nz, g=3.6, psi=PSI_EXP, solid_z=2, wall_rho=wall_rho))
+    a, b = li.film(1, 1, nz, 64)
+    o.init_from_density(a, b)
+    o.step(60000)
+    ra = o.density()[0][:, 0, 0]
+    rho_ma, rho_mi = ra[20:44].mean(), ra[84:108].mean()
+    print(f"wall_rho {wall_rho}: rho_ma = {rho_ma:.5f}, rho_mi = {rho_mi:.5f}, next to the wall "
+          f"{ra[2]:.5f}, {ra[3]:.5f}")
+    assert abs(rho_mi - 0.036) < 0.001, rho_mi
+    assert abs(rho_ma - 0.704) < 0.006, rho_ma
+
+
+@pytest.mark.parametrize("wall_rho", [(0.0, 0.7), (0.0, 0.0)])
+def test_diffusion_into_bath_with_solid_wall(wall_rho):
+    """Sec. III A with the wall as the paper places it: a solid layer of
+    thickness 2 behind 125 fluid planes, the evaporation boundary
+    (rho_H = 0.001) on the far fluid plane; the invading component follows the
+    finite-difference Fick solution (a zero-flux mirror half a node before
+    the first fluid plane) to 0.5 % of rho_H. A wall with the bath's
+    densities exerts no force (measured 0.14 %). A wall that does not
+    interact (psi_w = 0) leaves the bath's partner pulling the invading
+    component towards it: the first fluid plane adsorbs an excess (4.7 % of
+    rho_H), and beyond it the profile still follows Fick (0.21 %)."""
+    nf, h, rho_h = 125, 2, 0.001
+    o = Oracle(OracleParams(4, 4, nf + h, solid_z=h, wall_rho=wall_rho, g=3.6, psi=PSI_EXP, sink=SINK_ZMAX,
+                            rho_h=rho_h))
+    o.init_from_density(np.zeros((nf + h, 4, 4)), np.full((nf + h, 4, 4), 0.7))
+    D = an.diffusion_small_gradient(0.5 * rho_h, 0.7, 3.6, "exp")
+    T = 8000
+    o.step(T)
+    ra = o.density()[0][h:, 0, 0]
+    dev = (ra - an.fick_bath_fd(nf, rho_h, D, T)) / rho_h
+    if wall_rho[1] == 0.7:
+        assert np.max(np.abs(dev)) < 0.005, np.max(np.abs(dev))
+    else:
+        assert np.max(np.abs(dev[1:])) < 0.005, np.max(np.abs(dev[1:]))
+        assert 0.01 < dev[0] < 0.1, dev[0]
 
 
 # ---------------------------------------------------------------------------
