@@ -9,7 +9,9 @@ as the C oracle: moments and common velocity (Sec. II A), the Shan-Chen force
 streaming with periodic wrap or a bounce-back wall at the z seam, and the
 mass-conserving sink (Sec. II C). Solid wall nodes (Sec. III A, III B) hold
 no fluid, reflect every population a fluid neighbour would pull from them,
-and carry psi of given wall densities in the force.
+and carry psi of given wall densities in the force. With one component
+(ncomp=1, the multiphase form), the force takes the component itself as the
+partner and the sink holds it at rho_H, booking what it removes.
 """
 from __future__ import annotations
 
@@ -46,7 +48,7 @@ class ExactLattice:
     Parameters given as strings or integers are converted exactly."""
 
     def __init__(self, nx, ny, nz, g, tau=(1, 1), psi_kind="rho", wall_z=False, sink=None, rho_h=0, solid=None,
-                 wall_rho=(0, 0)):
+                 wall_rho=(0, 0), ncomp=2):
         self.dims = (nx, ny, nz)
         self.g = mpf(g)
         self.tau = (mpf(tau[0]), mpf(tau[1]))
@@ -55,6 +57,7 @@ class ExactLattice:
         self.sink = sink  # callable (x, y, z) -> bool, or None
         self.solid = solid  # callable (x, y, z) -> bool, or None
         self.wall_rho = (mpf(wall_rho[0]), mpf(wall_rho[1]))
+        self.ncomp = ncomp
         self.rho_h = mpf(rho_h)
         self.evaporated = mpf(0)
         self.nodes = [(x, y, z) for z in range(nz) for y in range(ny) for x in range(nx)]
@@ -72,8 +75,8 @@ class ExactLattice:
 
     def set_populations(self, pops):
         """pops[c][node][e] -> number; then the uncounted sink reset."""
-        self.f = [{n: {e: (mpf(0) if self.is_solid(n) else mpf(v)) for e, v in pops[c][n].items()}
-                   for n in self.nodes} for c in range(2)]
+        self.f = [{n: {e: (mpf(0) if self.is_solid(n) or c >= self.ncomp else mpf(v))
+                       for e, v in pops[c][n].items()} for n in self.nodes} for c in range(2)]
         self._reset(count=False)
 
     def density(self, c, node):
@@ -89,7 +92,8 @@ class ExactLattice:
             rb = self.density(1, n)
             rbh = ra + rb - self.rho_h
             self.f[0][n] = {e: feq(e, self.rho_h, (0, 0, 0)) for e in VELOCITIES}
-            self.f[1][n] = {e: feq(e, rbh, (0, 0, 0)) for e in VELOCITIES}
+            if self.ncomp == 2:
+                self.f[1][n] = {e: feq(e, rbh, (0, 0, 0)) for e in VELOCITIES}
             if count:
                 self.evaporated += ra - self.rho_h
 
@@ -122,13 +126,16 @@ class ExactLattice:
                 for e in VELOCITIES:
                     if e == (0, 0, 0):
                         continue
-                    pn = ps[1 - c][self._neighbour_for_psi(n, e)]
+                    pn = ps[c if self.ncomp == 1 else 1 - c][self._neighbour_for_psi(n, e)]
                     for d in range(3):
                         s[d] += weight(e) * pn * e[d]
                 force.append([-ps[c][n] * self.g * s[d] for d in range(3)])
             rt = rho[0][n] + rho[1][n]
             up = [(j[0][d] + j[1][d]) / rt for d in range(3)]
             for c in range(2):
+                if c >= self.ncomp:
+                    post[c][n] = {e: mpf(0) for e in VELOCITIES}
+                    continue
                 if rho[c][n] != 0:
                     u = [up[d] + self.tau[c] * force[c][d] / rho[c][n] for d in range(3)]
                 else:
@@ -168,11 +175,11 @@ class ExactLattice:
                 continue
             num = [sum(self.f[c][n][e] * e[d] for c in range(2) for e in VELOCITIES) for d in range(3)]
             if not self.is_sink(n):
-                for c in range(2):
+                for c in range(self.ncomp):
                     for e in VELOCITIES:
                         if e == (0, 0, 0):
                             continue
-                        pn = ps[1 - c][self._neighbour_for_psi(n, e)]
+                        pn = ps[c if self.ncomp == 1 else 1 - c][self._neighbour_for_psi(n, e)]
                         for d in range(3):
                             num[d] += -ps[c][n] * self.g * weight(e) * pn * e[d] / 2
             rt = rho[0][n] + rho[1][n]

@@ -42,7 +42,14 @@
  *   - at rho^c = 0 the force shift is taken as zero (f^eq is then zero for
  *     any finite velocity);
  *   - a sink switched on mid-run is skipped by the next collision and resets
- *     its nodes at the end of that step.
+ *     its nodes at the end of that step;
+ *   - the single-component multiphase form (Sec. I: the method carries over to
+ *     "the multiphase pseudopotential method"): one component whose force of
+ *     Eq. (sc) takes itself as the partner with the coupling g (negative for
+ *     attraction); the evaporation boundary holds it at rho_H with zero
+ *     velocity, and with no partner to take the difference the removed mass
+ *     leaves the system and is booked as E (Sec. II C: the model extends to
+ *     situations where mass is not conserved).
  */
 #include <math.h>
 #include <stdint.h>
@@ -75,6 +82,7 @@ typedef struct {
     double phi_delta[2]; /* (rhoA - rhoB) inside / outside a droplet */
     int solid_z;       /* solid wall nodes at z = 0 .. solid_z - 1 (0: none) */
     double wall_rho[2];  /* densities whose psi the solid nodes carry */
+    int ncomp;         /* components: 2 (also 0) or 1 (single-component multiphase) */
 } orc_params;
 
 typedef struct {
@@ -185,6 +193,13 @@ static int is_sink(const orc_params *p, int x, int y, int z)
     }
 }
 
+/* Components stepped: 1 or 2. With one, component 1 stays empty. */
+static int ncomp(const orc_params *p) { return p->ncomp == 1 ? 1 : 2; }
+
+/* The partner in the force of Eq. (sc): the other component, or with one
+ * component the component itself. */
+static int partner(const orc_params *p, int c) { return ncomp(p) == 1 ? c : 1 - c; }
+
 /* Solid wall node (the layer z < solid_z). */
 static int is_solid(const orc_params *p, int z) { return z < p->solid_z; }
 
@@ -194,6 +209,7 @@ orc_lattice *orc_create(const orc_params *p)
 {
     if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0) return NULL;
     if (p->solid_z < 0 || p->solid_z >= p->nz || (p->solid_z > 0 && p->wall_z)) return NULL;
+    if (p->ncomp != 0 && p->ncomp != 1 && p->ncomp != 2) return NULL;
     orc_lattice *L = (orc_lattice *)calloc(1, sizeof(orc_lattice));
     if (!L) return NULL;
     L->p = *p;
@@ -244,7 +260,7 @@ static double apply_sink(orc_lattice *L)
                 double rb_h = ra + rb - p->rho_h;
                 for (int i = 0; i < NQ; ++i) {
                     L->f[(0 * NQ + i) * n + k] = feq(i, p->rho_h, 0.0, 0.0, 0.0);
-                    L->f[(1 * NQ + i) * n + k] = feq(i, rb_h, 0.0, 0.0, 0.0);
+                    if (ncomp(p) == 2) L->f[(1 * NQ + i) * n + k] = feq(i, rb_h, 0.0, 0.0, 0.0);
                 }
                 L->flux[k] = ra - p->rho_h;
             }
@@ -255,12 +271,15 @@ static double apply_sink(orc_lattice *L)
 
 /* ---- initialisation ------------------------------------------------------ */
 
-/* Solid nodes hold no fluid: their populations are zero. */
+/* Solid nodes hold no fluid: their populations are zero; so are those of an
+ * absent second component. */
 static void clear_solid(orc_lattice *L)
 {
     const long long n = L->n, plane = (long long)L->p.nx * L->p.ny;
     for (int q = 0; q < 2 * NQ; ++q)
         for (long long k = 0; k < (long long)L->p.solid_z * plane; ++k) L->f[q * n + k] = 0.0;
+    if (ncomp(&L->p) == 1)
+        for (long long q = NQ * n; q < 2 * NQ * n; ++q) L->f[q] = 0.0;
 }
 
 /* f = f^eq(rho, 0) at every node, then the initial sink reset, which is not
@@ -326,7 +345,7 @@ static double psi_neighbour(const orc_lattice *L, int c, int x, int y, int z, in
 /* Eq. (sc) with one partner component: F^c = -psi^c g sum_i w_i psi^cbar e_i. */
 static void sc_force(const orc_lattice *L, int c, int x, int y, int z, double F[3])
 {
-    int cb = 1 - c;
+    int cb = partner(&L->p, c);
     double sx = 0.0, sy = 0.0, sz = 0.0;
     for (int i = 1; i < NQ; ++i) {
         double ps = psi_neighbour(L, cb, x, y, z, i);
@@ -370,8 +389,9 @@ static void collide(orc_lattice *L)
                     for (int q = 0; q < 2 * NQ; ++q) L->fs[q * n + k] = L->f[q * n + k];
                     continue;
                 }
-                double rho[2], j[2][3], F[2][3];
-                for (int c = 0; c < 2; ++c) {
+                const int nc = ncomp(p);
+                double rho[2] = {0.0, 0.0}, j[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}}, F[2][3];
+                for (int c = 0; c < nc; ++c) {
                     rho[c] = L->rho[c * n + k];
                     momentum_of(L, c, k, j[c]);
                     sc_force(L, c, x, y, z, F[c]);
@@ -380,7 +400,8 @@ static void collide(orc_lattice *L)
                 double rt = rho[0] + rho[1];
                 double up[3];
                 for (int d = 0; d < 3; ++d) up[d] = (j[0][d] + j[1][d]) / rt;
-                for (int c = 0; c < 2; ++c) {
+                for (int q = nc * NQ; q < 2 * NQ; ++q) L->fs[q * n + k] = 0.0;
+                for (int c = 0; c < nc; ++c) {
                     double u[3];
                     for (int d = 0; d < 3; ++d)
                         u[d] = up[d] + (rho[c] != 0.0 ? p->tau[c] * F[c][d] / rho[c] : 0.0);
@@ -471,7 +492,7 @@ void orc_get_velocity(orc_lattice *L, double *out3)
                     for (int d = 0; d < 3; ++d) out3[d * n + k] = 0.0;
                     continue;
                 }
-                for (int c = 0; c < 2; ++c) {
+                for (int c = 0; c < ncomp(p); ++c) {
                     double j[3], F[3] = {0.0, 0.0, 0.0};
                     momentum_of(L, c, k, j);
                     if (!is_sink(p, x, y, z)) sc_force(L, c, x, y, z, F);
@@ -491,7 +512,7 @@ void orc_total_force(orc_lattice *L, double out[3])
     for (int z = 0; z < p->nz; ++z)
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x)
-                for (int c = 0; c < 2; ++c) {
+                for (int c = 0; c < ncomp(p); ++c) {
                     double F[3];
                     if (is_solid(p, z)) continue;
                     sc_force(L, c, x, y, z, F);
@@ -526,15 +547,20 @@ void orc_diagnostics(orc_lattice *L, orc_diag *out)
                     for (int d = 0; d < 3; ++d) out->momentum[d] += j[d];
                 }
                 if (!isfinite(ra) || !isfinite(rb)) out->nonfinite += 1;
-                if (ra <= 0.0 || rb <= 0.0) out->nonpositive += 1;
-                prof[z] += ra - rb;
-                double phi = (ra - rb - p->phi_delta[1]) / (p->phi_delta[0] - p->phi_delta[1]);
+                if (ra <= 0.0 || (ncomp(p) == 2 && rb <= 0.0)) out->nonpositive += 1;
+                /* the order parameter: rhoA - rhoB, or with one component its
+                 * density, against the midpoint of the two phases */
+                double q = ncomp(p) == 2 ? ra - rb : ra;
+                prof[z] += ncomp(p) == 2 ? q : q - 0.5 * (p->phi_delta[0] + p->phi_delta[1]);
+                double phi = (q - p->phi_delta[1]) / (p->phi_delta[0] - p->phi_delta[1]);
                 if (phi < 0.0) phi = 0.0;
                 if (phi > 1.0) phi = 1.0;
                 phisum += phi;
             }
-    /* Interface: first sign change of the plane-averaged rhoA - rhoB scanning
-     * up from the lowest fluid plane, located by linear interpolation. */
+    /* Interface: first sign change of the plane-averaged order parameter
+     * (rhoA - rhoB, or one component's density minus the midpoint of its
+     * phases) scanning up from the lowest fluid plane, located by linear
+     * interpolation. */
     out->z_interface = NAN;
     double area = (double)p->nx * p->ny;
     for (int z = p->solid_z; z + 1 < p->nz; ++z) {

@@ -49,6 +49,7 @@ class _Params(ctypes.Structure):
         ("phi_delta", ctypes.c_double * 2),
         ("solid_z", ctypes.c_int),
         ("wall_rho", ctypes.c_double * 2),
+        ("ncomp", ctypes.c_int),
     ]
 
 
@@ -143,6 +144,7 @@ class OracleParams:
     phi_delta: tuple = (0.66, -0.66)
     solid_z: int = 0
     wall_rho: tuple = (0.0, 0.0)
+    ncomp: int = 2
 
 
 class Oracle:
@@ -156,7 +158,7 @@ class Oracle:
         c = p.center if p.center is not None else ((p.nx - 1) / 2, (p.ny - 1) / 2, (p.nz - 1) / 2)
         cp = _Params(p.nx, p.ny, p.nz, int(p.wall_z), (ctypes.c_double * 2)(*p.tau), p.g, p.psi, p.sink,
                      p.rho_h, p.sink_radius, (ctypes.c_double * 3)(*c), (ctypes.c_double * 2)(*p.phi_delta),
-                     int(p.solid_z), (ctypes.c_double * 2)(*p.wall_rho))
+                     int(p.solid_z), (ctypes.c_double * 2)(*p.wall_rho), int(p.ncomp))
         self._h = lib.orc_create(ctypes.byref(cp))
         if not self._h:
             raise ValueError("oracle: invalid lattice parameters")
@@ -168,8 +170,11 @@ class Oracle:
             self._lib.orc_destroy(h)
             self._h = None
 
-    def init_from_density(self, rho_a: np.ndarray, rho_b: np.ndarray):
+    def init_from_density(self, rho_a: np.ndarray, rho_b: np.ndarray = None):
+        """rho_b is ignored (may be None) for one component."""
         a = np.ascontiguousarray(rho_a, dtype=np.float64).reshape(-1)
+        if rho_b is None:
+            rho_b = np.zeros_like(a)
         b = np.ascontiguousarray(rho_b, dtype=np.float64).reshape(-1)
         assert a.size == self.n and b.size == self.n
         self._lib.orc_init_from_density(self._h, _dp(a), _dp(b))
