@@ -74,6 +74,15 @@ enum { LBSC_PSI_RHO = 0, LBSC_PSI_EXP = 1 };
 /* Sink node sets: the plane z = nz-1; the six faces; all nodes at distance
  * >= sink_radius from center. */
 enum { LBSC_SINK_NONE = 0, LBSC_SINK_ZMAX = 1, LBSC_SINK_FACES = 2, LBSC_SINK_SPHERE = 3 };
+/* Option bits of lbsc_params.flags.
+ * LBSC_FLAG_FP16S_SINK: accept FP16S storage together with an evaporation
+ * sink. Without it that combination is refused with LBSC_E_UNSUPPORTED: with
+ * a constant shift, FP16 rounds away the small per-step changes of slow
+ * diffusion, so the vapour near the sink stops relaxing, the sink keeps
+ * booking a flux that never leaves the droplet and M^A + E drifts from
+ * M^A(0) (use FP16N, which stores a per-node shift). The flag exists to test
+ * the FP16S code paths. */
+enum { LBSC_FLAG_FP16S_SINK = 1 };
 
 typedef struct lbsc_params {
     int32_t nx, ny, nz;      /* lattice size, each 1..4096, nx*ny*nz < 2^31 and
@@ -94,20 +103,55 @@ typedef struct lbsc_params {
     double center[3];        /* sphere centre (x, y, z) in node units */
     double phi_delta[2];     /* rhoA - rhoB inside / outside a droplet, for the
                                 volume-fraction radius diagnostic */
+    int32_t solid_z;         /* thickness h >= 0 of a solid wall occupying the
+                                planes z = 0 .. h-1 (Sec. III A, III B: walls of
+                                thickness 2 at the bottom of the film). Fluid
+                                links into solid nodes bounce back half-way
+                                ("inverting velocities", Sec. II A): below
+                                z = h and, through the periodic z wrap, above
+                                z = nz-1. Solid nodes hold no fluid; in the
+                                force of Eq. (sc) they count with
+                                psi(wall_rho[c]). Excludes wall_z; needs
+                                nz > h. */
+    int32_t flags;           /* LBSC_FLAG_* bits */
+    double wall_rho[2];      /* densities of solid nodes in the force of
+                                Eq. (sc) (0, 0: the wall does not interact) */
+    int32_t ncomp;           /* components: 2 (also 0), or 1 for the
+                                single-component multiphase form the method
+                                carries over to (Sec. I): the force of
+                                Eq. (sc) takes the component itself as the
+                                partner with coupling g (g < 0 attracts), and
+                                the sink holds it at rho_H with zero velocity;
+                                with no partner the removed mass leaves the
+                                system and is booked as E (Sec. II C). Uses
+                                tau[0], shift[0], wall_rho[0]; phi_delta holds
+                                the liquid and vapour densities (the interface
+                                is where rho crosses their midpoint). FP64 or
+                                FP32S only (LBSC_E_UNSUPPORTED otherwise); all
+                                instances of a context alike. */
+    int32_t reserved;        /* 0 */
 } lbsc_params;
 
+/* FP64 diagnostics of one instance (Sec. II C for the sink bookkeeping,
+ * Sec. III B for the film's interface position, Sec. III C for the droplet
+ * radius). Solid wall nodes are left out of every sum. */
 typedef struct lbsc_diag {
     int64_t step;            /* time steps taken since the last init */
     double mass[2];          /* sum over nodes of rho^A, rho^B */
-    double evaporated;       /* mass of A removed by the sink since init */
+    double evaporated;       /* mass of A removed by the sink since init: the
+                                sum over resets of rhoA_pre - rho_H (Sec. II C) */
     double evap_rate;        /* sum over sink nodes of (rhoA_pre - rho_H) in the
                                 reset that formed the current state */
     double momentum[3];      /* sum over nodes and components of j^c */
-    double z_interface;      /* first zero of the plane mean of rhoA - rhoB,
-                                scanning up from z = 0, linearly interpolated;
+    double z_interface;      /* x_I of Sec. III B, where rhoA - rhoB = 0: the
+                                first zero of its plane mean, scanning up from
+                                the lowest fluid plane, linearly interpolated;
                                 NaN if none */
-    double r_droplet;        /* (3 V / 4 pi)^(1/3), V = sum of the clamped
-                                volume fraction of A */
+    double r_droplet;        /* the droplet radius R_I of Sec. III C, taken as
+                                (3 V / 4 pi)^(1/3) with V the sum of the
+                                clamped volume fraction of A,
+                                (rhoA - rhoB - phi_delta[1]) /
+                                (phi_delta[0] - phi_delta[1]) */
     int64_t nonfinite;       /* nodes with a non-finite density */
     int64_t nonpositive;     /* nodes with a density <= 0 */
 } lbsc_diag;
@@ -154,14 +198,21 @@ lbsc_status lbsc_bind(lbsc_ctx* ctx, void* pop0, void* pop1, void* scratch);
 lbsc_status lbsc_set_stream(lbsc_ctx* ctx, void* hip_stream);
 
 /* Initial state f = f^eq(rho, 0) of instance inst from two FP64 device arrays
- * of nx*ny*nz densities, then the initial sink reset, which is not counted as
+ * of nx*ny*nz densities (rhoB is ignored, and may be NULL, with one
+ * component), then the initial sink reset, which is not counted as
  * evaporated mass. Resets the step counter and the evaporated mass. */
 lbsc_status lbsc_init_from_density(lbsc_ctx* ctx, int32_t inst, const double* rhoA_dev, const double* rhoB_dev);
-/* As above from full FP64 device populations f[(c*19 + i)*n + node]. */
+/* As above from full FP64 device populations f[(c*19 + i)*n + node]
+ * (f[i*n + node] with one component). */
 lbsc_status lbsc_init_from_populations(lbsc_ctx* ctx, int32_t inst, const double* f_dev);
 
-/* Changes the sink of instance inst (kind, rho_H, sphere radius). Its nodes
- * skip the next collision; they are reset at the end of that step. */
+/* Changes the evaporation sink of instance inst (kind, rho_H, sphere
+ * radius): the boundary of Sec. II C that holds component A at rho_H and
+ * gives B the rest of the node's density, both at zero velocity. Its nodes
+ * skip the next collision; they are reset at the end of that step (the
+ * workflow of Sec. III B, III C: equilibrate, then impose rho_H). FP16S
+ * storage refuses a sink (LBSC_E_UNSUPPORTED) unless the instance was created
+ * with LBSC_FLAG_FP16S_SINK. */
 lbsc_status lbsc_set_sink(lbsc_ctx* ctx, int32_t inst, int32_t kind, double rho_h, double radius);
 
 /* Advances every instance by n time steps. */
@@ -178,10 +229,34 @@ lbsc_status lbsc_get_tiles(const lbsc_ctx* ctx, lbsc_tiles* out);
  * lengths; chunks of 1, 2 and 4 planes only for contexts of fewer than 2^22
  * nodes) for `steps` steps each (steps >= 2), re-times the three fastest
  * over three times as many steps, and keeps the best; writes it to *chosen
- * if non-NULL.
- * The populations advance during tuning (every schedule gives the same
- * bits), so call it before lbsc_init_*. The graph setting is kept. */
+ * if non-NULL. A context of several instances then tunes per size class
+ * (boxes whose larger side is < 64, < 96, < 128, < 192, or more): each
+ * class's tile width and chunk length (lbsc_set_inst_tiles) that make the
+ * whole context's step fastest, one class after the other.
+ * Results go to a process-wide cache keyed by (GPU architecture, lattice
+ * size, precision, components, and for a batch the context's nt and
+ * variant), valid for this build's kernel sources (lbsc_kernel_hash): a
+ * one-instance context, or a size class whose every instance is cached,
+ * takes its schedule from the cache without timing. The populations advance
+ * during tuning (every schedule gives the same bits) and the evaporation
+ * accumulators are left undefined, so call it before lbsc_init_*. The
+ * graph setting is kept. */
 lbsc_status lbsc_tune(lbsc_ctx* ctx, int32_t steps, lbsc_tiles* chosen);
+/* Tile width, rows and chunk length of instance inst (tiles->tw, th, nzc;
+ * 0 = the context's; nt and variant are the context's), replacing the
+ * context's for that instance only; lbsc_get_inst_tiles reads them back with
+ * the context's resolved nt and variant. */
+lbsc_status lbsc_set_inst_tiles(lbsc_ctx* ctx, int32_t inst, const lbsc_tiles* tiles);
+lbsc_status lbsc_get_inst_tiles(const lbsc_ctx* ctx, int32_t inst, lbsc_tiles* out);
+/* The tuning cache as text (one line per entry, tagged with the kernel
+ * source hash): save writes every entry; load adds the entries of this
+ * build's kernel sources (others are skipped) and reports their number;
+ * clear empties it. */
+lbsc_status lbsc_tune_cache_save(const char* path);
+lbsc_status lbsc_tune_cache_load(const char* path, int32_t* n_loaded);
+void lbsc_tune_cache_clear(void);
+/* Hash of the kernel sources' code this library was built from. */
+const char* lbsc_kernel_hash(void);
 /* Number of work items (blocks per step) of the current schedule. */
 lbsc_status lbsc_num_items(const lbsc_ctx* ctx, int32_t* n_items);
 
@@ -190,7 +265,8 @@ lbsc_status lbsc_num_items(const lbsc_ctx* ctx, int32_t* n_items);
  * densities of both components and the barycentric velocity U of Eq. (velw)
  * (out_u[d*n + node], d = x, y, z; any of the three pointers may be NULL
  * except that U needs both density arrays); all populations f[(c*19+i)*n +
- * node]. */
+ * node]. With one component: comp 0 only, rhoB (if given) is zero, U needs
+ * rhoA, and the populations are f[i*n + node]. */
 lbsc_status lbsc_read_density(lbsc_ctx* ctx, int32_t inst, int32_t comp, double* out_dev);
 lbsc_status lbsc_read_observables(lbsc_ctx* ctx, int32_t inst, double* rhoA_dev, double* rhoB_dev, double* u_dev);
 lbsc_status lbsc_read_populations(lbsc_ctx* ctx, int32_t inst, double* f_dev);

@@ -138,3 +138,28 @@ def fick_bath_fd(nz: int, rho_h: float, D: float, T: float, dt: float = 0.05):
         lap[0] = u[1] - u[0]
         u[:-1] += dt * D * lap
     return u
+
+
+def coexistence_single(G, guess=(0.1, 2.0)):
+    """Liquid-vapour coexistence of the single-component model with psi = 1 -
+    exp(-rho): equal bulk pressure p = c_s^2 rho + c_s^2 G psi^2 / 2 and
+    int (p0 - p) psi' / psi^2 d rho = 0 over [rho_v, rho_l]. Both follow from
+    mechanical equilibrium of a planar interface when the neighbour sum of
+    Eq. (sc) is expanded to third order on a lattice isotropic to fourth
+    order: the force's gradient term, psi times the third derivative of psi,
+    divided by psi is an exact derivative."""
+    from scipy.integrate import quad
+    from scipy.optimize import fsolve
+    cs2 = 1.0 / 3.0
+
+    def psi(r):
+        return 1.0 - np.exp(-r)
+
+    def p(r):
+        return cs2 * r + cs2 * G / 2 * psi(r) ** 2
+
+    def eqs(v):
+        rv, rl = v
+        p0 = p(rv)
+        return [p(rl) - p0, quad(lambda r: (p0 - p(r)) * np.exp(-r) / psi(r) ** 2, rv, rl)[0]]
+    return fsolve(eqs, guess)

@@ -142,11 +142,13 @@ template <> struct Par<double> {
     static __device__ __forceinline__ double shift(const Inst& I, int c) { return I.shift[c]; }
     static __device__ __forceinline__ double omega(const Inst& I, int c) { return I.omega[c]; }
     static __device__ __forceinline__ double ntg(const Inst& I, int c) { return -I.tau[c] * I.g; }
+    static __device__ __forceinline__ double psiw(const Inst& I, int c) { return I.psi_w[c]; }
 };
 template <> struct Par<float> {
     static __device__ __forceinline__ float shift(const Inst& I, int c) { return I.shift_f[c]; }
     static __device__ __forceinline__ float omega(const Inst& I, int c) { return I.omega_f[c]; }
     static __device__ __forceinline__ float ntg(const Inst& I, int c) { return I.ntg_f[c]; }
+    static __device__ __forceinline__ float psiw(const Inst& I, int c) { return I.psi_wf[c]; }
 };
 
 template <typename A>
@@ -502,13 +504,101 @@ __device__ __forceinline__ void absorb_rest(A (&f)[kQ], A total)
     f[0] = total - moving;
 }
 
-// Sink reset (Sec. II C): A -> f^eq(rho_H, 0), B -> f^eq(rhoA + rhoB - rho_H, 0)
-// from the densities pulled in this step. Returns rhoA_pre - rho_H in FP64.
+// Mass bookkeeping of FP32 storage (FP32S). Rounding the rest population to
+// nearest would change a node's stored mass by up to half an FP32 ulp with
+// the same sign at every node of a uniform region, a drift that grows with
+// the region's volume and the number of steps. The rest instead takes the
+// node's exact residual, rounded stochastically: unbiased, with a draw that
+// hashes the node and the value being rounded (deterministic, the same in
+// every kernel variant, uncorrelated between nodes), so the stored mass
+// changes only by a zero-mean error per node and step.
+//  - Collision: the residual is f_0 + sum_{i>0} (f_i - f'_i), the pre-collision
+//    rest plus the moving populations' increments. The increments are small
+//    near equilibrium, so their FP32 differences and sum carry errors far
+//    below the rest's ulp; a TwoSum gives the exact remainder to round.
+//  - Sink reset: the node's stored mass is summed exactly in FP64 (19 FP32
+//    values; their exponents span far less than FP64's extra 29 bits) and E
+//    books the exact change of its A mass.
+template <class S> constexpr bool kExact = std::is_same_v<S, StF32S>;
+
 template <typename A>
-__device__ __forceinline__ double sink_reset(const Inst& I, NodeVals<A>& v)
+__device__ __forceinline__ double sum64(const A (&f)[kQ], int from = 0)
+{
+    double m = 0.0;
+#pragma unroll
+    for (int i = from; i < kQ; ++i) m += (double)f[i];
+    return m;
+}
+
+// 32-bit avalanche of the MurmurHash3 finaliser (Appleby), public domain.
+__host__ __device__ __forceinline__ uint32_t fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+// x rounded to FP32 up or down with probabilities that make the result's
+// expectation x, from the draw hash(key, bits of x).
+__host__ __device__ __forceinline__ float round_sr(double x, uint32_t key)
+{
+    const float f = (float)x;
+    const double r = x - (double)f;   // exact
+    const uint64_t xb = __builtin_bit_cast(uint64_t, x);
+    const uint32_t h = fmix32(key ^ fmix32((uint32_t)xb ^ (uint32_t)(xb >> 32)));
+    // the FP32 neighbour of f on the side of x
+    uint32_t b = __builtin_bit_cast(uint32_t, f);
+    if (f == 0.0f) b = r > 0.0 ? 1u : 0x80000001u;
+    else b += ((r > 0.0) == (f > 0.0f)) ? 1u : 0xffffffffu;
+    const float g = __builtin_bit_cast(float, b);
+    const double gap = __builtin_fabs((double)g - (double)f);
+    const double u = (double)(h >> 8) * (1.0 / 16777216.0);
+    return (r != 0.0 && u * gap < __builtin_fabs(r)) ? g : f;
+}
+
+// a + b rounded to FP32 stochastically: the exact sum is s + r (TwoSum),
+// and s moves one ulp towards r with probability |r| / ulp, from the draw
+// hash(key, bits of s and r). The gap to the neighbour is a power of two, so
+// u * gap is exact.
+__host__ __device__ __forceinline__ float round_sr_sum(float a, float b, uint32_t key)
+{
+    const float s = a + b;
+    const float bb = s - a;
+    const float r = (a - (s - bb)) + (b - bb);
+    uint32_t sb = __builtin_bit_cast(uint32_t, s);
+    if (s == 0.0f) sb = r > 0.0f ? 1u : 0x80000001u;
+    else sb += ((r > 0.0f) == (s > 0.0f)) ? 1u : 0xffffffffu;
+    const float g = __builtin_bit_cast(float, sb);
+    const float gap = __builtin_fabsf(g - s);
+    const uint32_t h = fmix32(key ^ fmix32(__builtin_bit_cast(uint32_t, s) ^ (__builtin_bit_cast(uint32_t, r) << 1)));
+    const float u = (float)(h >> 8) * (1.0f / 16777216.0f);
+    return (r != 0.0f && u * gap < __builtin_fabsf(r)) ? g : s;
+}
+
+// Rest population of an FP32S node whose stored deviations must sum to m
+// (exact FP64): m minus the exact sum of the moving ones, rounded
+// stochastically.
+__device__ __forceinline__ void absorb_rest_exact(float (&f)[kQ], double m, uint32_t key)
+{
+    f[0] = round_sr(m - sum64(f, 1), key);
+}
+
+// Sink reset (Sec. II C): A -> f^eq(rho_H, 0), B -> f^eq(rhoA + rhoB - rho_H, 0)
+// from the densities pulled in this step. Returns rhoA_pre - rho_H in FP64:
+// for FP32S the exact change of the node's stored A mass (its new stored
+// density is rho_H up to the rest's zero-mean rounding), otherwise from the
+// exact FP64 sum of the pulled deviations. key: the node's index, for the
+// stochastic rounding.
+template <typename A, bool EX = false>
+__device__ __forceinline__ double sink_reset(const Inst& I, NodeVals<A>& v, uint32_t key)
 {
     const double rho_h = I.reset.rho_h;
-    const double flux = I.shift[0] + (double)v.drho[0] - rho_h;
+    const double ma = kPlain<A> ? (double)v.drho[0] : sum64(v.f[0]);
+    const double mb = kPlain<A> ? (double)v.drho[1] : sum64(v.f[1]);
+    double flux = I.shift[0] + ma - rho_h;
     // rho_H - rho0^A is exact in FP64; the partner deviation
     // rhoB_H - rho0^B = (rho0^A - rho_H) + drho^A + drho^B is formed from
     // small terms, so no O(1) density is rounded.
@@ -517,13 +607,22 @@ __device__ __forceinline__ double sink_reset(const Inst& I, NodeVals<A>& v)
     // formed here, at the (few) sink nodes, not hoisted out of the march
     // into 19 registers.
     asm volatile("" : "+v"(da));
-    const A db = (A)(I.shift[0] - rho_h) + v.drho[0] + v.drho[1];
+    A db;
+    if constexpr (EX) db = (A)(I.shift[0] - rho_h + ma + mb);
+    else db = (A)(I.shift[0] - rho_h) + v.drho[0] + v.drho[1];
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
         v.f[0][i] = (A)wgt(i) * da;
         v.f[1][i] = (A)wgt(i) * db;
     }
-    if constexpr (!kPlain<A>) {
+    if constexpr (EX) {
+        // A takes rho_H exactly up to its rest's rounding; B the rest of
+        // the node's stored mass; E books the exact change of A.
+        absorb_rest_exact(v.f[0], rho_h - I.shift[0], key * 2u);
+        const double ma_new = sum64(v.f[0]);
+        absorb_rest_exact(v.f[1], ma + mb - ma_new, key * 2u + 1u);
+        flux = ma - ma_new;
+    } else if constexpr (!kPlain<A>) {
         // FP32 weights do not sum to 1 exactly; the rest population takes
         // the residual so each component holds exactly its reset density.
         absorb_rest(v.f[0], da);
@@ -543,8 +642,9 @@ template <typename A> __device__ __forceinline__ A recip(A x);
 template <> __device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
 template <> __device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
-template <typename A>
-__device__ __forceinline__ void collide_node(const Inst& I, NodeVals<A>& v, const A S[2][3], A psiA, A psiB)
+template <typename A, bool EX = false>
+__device__ __forceinline__ void collide_node(const Inst& I, NodeVals<A>& v, const A S[2][3], A psiA, A psiB,
+                                             uint32_t key)
 {
     A j[2][3];
 #pragma unroll
@@ -584,7 +684,11 @@ __device__ __forceinline__ void collide_node(const Inst& I, NodeVals<A>& v, cons
         const A omega = Par<A>::omega(I, c);
         // Rest: f^eq_0 = w_0 (drho + rho (-1.5 u.u)) in deviation form.
         const A base0 = drho - (A)1.5 * rho * uu;
+        const A f0 = v.f[c][0];
         v.f[c][0] = v.f[c][0] - (v.f[c][0] - (A)wgt(0) * base0) * omega;
+        // FP32S: the moving populations' increments, to give the rest the
+        // node's exact stored mass (see absorb_rest_sr)
+        A dsum = (A)0;
         // Opposite pairs (i, i+1) share w, |e.u| and the even part of q.
 #pragma unroll
         for (int i = 1; i < kQ; i += 2) {
@@ -592,11 +696,17 @@ __device__ __forceinline__ void collide_node(const Inst& I, NodeVals<A>& v, cons
             const A even = (A)wgt(i) * (base0 + (A)4.5 * rho * eu * eu);
             const A odd = (A)wgt(i) * (A)3 * rho * eu;
             const A fp = even + odd, fm = even - odd;
-            v.f[c][i] = v.f[c][i] - (v.f[c][i] - fp) * omega;
-            v.f[c][i + 1] = v.f[c][i + 1] - (v.f[c][i + 1] - fm) * omega;
+            const A a = v.f[c][i], b = v.f[c][i + 1];
+            v.f[c][i] = a - (a - fp) * omega;
+            v.f[c][i + 1] = b - (b - fm) * omega;
+            if constexpr (EX) {
+                dsum += a - v.f[c][i];
+                dsum += b - v.f[c][i + 1];
+            }
         }
         // BGK conserves each component's mass exactly (sum_i f^eq_i = rho).
-        if constexpr (!kPlain<A>) absorb_rest(v.f[c], drho);
+        if constexpr (EX) v.f[c][0] = round_sr_sum(f0, dsum, key * 2u + (uint32_t)c);
+        else if constexpr (!kPlain<A>) absorb_rest(v.f[c], drho);
     }
 }
 
@@ -661,6 +771,13 @@ __device__ __forceinline__ void ring_coord(int r, int tw, int th, int& fx, int& 
     if (r < th) { fx = -1; fy = r; return; }
     r -= th;
     fx = tw; fy = r;
+}
+
+// Index of node (x, y, z) in the kernels' lattice: the key of its rest
+// populations' stochastic rounding (FP32S).
+__device__ __forceinline__ uint32_t node_key(const Inst& I, int x, int y, int z)
+{
+    return ((uint32_t)z * (uint32_t)I.ny + (uint32_t)y) * (uint32_t)I.nx + (uint32_t)x;
 }
 
 __device__ __forceinline__ int xcd_item(int b, int n_items)
@@ -729,6 +846,7 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
     // Halo nodes first, so only one extra population set is live at a time.
     auto load_plane = [&](int zq, int sl, NodeVals<A>& keep_or_tmp) {
         const int zp = psi_plane(zq, I.nz, I.wall_z);
+        const bool wallc = beyond_wall(I, zq);
         for (int r = t; r < nring; r += NT) {
             int fx, fy;
             ring_coord(r, tw, th, fx, fy);
@@ -736,9 +854,10 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
             NodeVals<A> h;
             pull_node<St>(s, I, hx, hy, zp, h);
             node_density<A>(I, h);
-            if (in_sink(I.reset, hx, hy, zp, I.nx, I.ny, I.nz)) sink_reset<A>(I, h);
+            if (in_sink(I.reset, hx, hy, zp, I.nx, I.ny, I.nz)) sink_reset<A, kExact<St>>(I, h, node_key(I, hx, hy, zp));
             const int fi = (fy + 1) * row + fx + 1;
-            psiS[sl].put(fi, psi_of<A>(h.rho[0], I.psi_exp), psi_of<A>(h.rho[1], I.psi_exp));
+            if (wallc) psiS[sl].put(fi, Par<A>::psiw(I, 0), Par<A>::psiw(I, 1));
+            else psiS[sl].put(fi, psi_of<A>(h.rho[0], I.psi_exp), psi_of<A>(h.rho[1], I.psi_exp));
         }
         if (own) {
             NodeVals<A> tmp;
@@ -746,11 +865,12 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
             pull_node<St>(s, I, x, y, zp, keep);
             node_density<A>(I, keep);
             if (in_sink(I.reset, x, y, zp, I.nx, I.ny, I.nz)) {
-                const double fl = sink_reset<A>(I, keep);
+                const double fl = sink_reset<A, kExact<St>>(I, keep, node_key(I, x, y, zp));
                 if (book && zq >= z0 && zq < z1) eflux += fl;
             }
             const int fi = (ty + 1) * row + tx + 1;
-            psiS[sl].put(fi, psi_of<A>(keep.rho[0], I.psi_exp), psi_of<A>(keep.rho[1], I.psi_exp));
+            if (wallc) psiS[sl].put(fi, Par<A>::psiw(I, 0), Par<A>::psiw(I, 1));
+            else psiS[sl].put(fi, psi_of<A>(keep.rho[0], I.psi_exp), psi_of<A>(keep.rho[1], I.psi_exp));
         }
     };
 
@@ -762,7 +882,7 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
         if constexpr (!KEEP) {
             pull_node<St>(s, I, x, y, z, v);
             node_density<A>(I, v);
-            if (in_sink(I.reset, x, y, z, I.nx, I.ny, I.nz)) sink_reset<A>(I, v);
+            if (in_sink(I.reset, x, y, z, I.nx, I.ny, I.nz)) sink_reset<A, kExact<St>>(I, v, node_key(I, x, y, z));
         }
         const int sm = (z - z0) % 3, s0 = (z - z0 + 1) % 3, sp = (z - z0 + 2) % 3;
         const uint32_t xy = (uint32_t)y * (uint32_t)I.nx + (uint32_t)x;
@@ -772,7 +892,7 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
             force_sum<A>(psiS[sm], psiS[s0], psiS[sp], cI, rI, row, S);
             const int fc = (ty + 1) * row + tx + 1;
             const Psi2<A> pc = psiS[s0].get(fc);
-            collide_node<A>(I, v, S, pc[0], pc[1]);
+            collide_node<A, kExact<St>>(I, v, S, pc[0], pc[1], node_key(I, x, y, z));
         }
         store_node<St>(d, I, z, xy, v);
     };
@@ -986,6 +1106,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<S
     // booked.
     auto dens_with = [&](int zq, auto&& ring_decode, NodeVals<A>& v) {
         const int zp = psi_plane(zs + dz * zq, I.nz, I.wall_z);
+        // behind a solid wall the plane's psi is the wall's (its loads, of
+        // the mirrored plane, are reduced as usual and left unused)
+        const bool wallc = beyond_wall(I, zs + dz * zq);
         auto& ps = psiS[(zq - z0 + 1) & 3];
         const uint32_t fi = tinfo[2][t];
         double fl = 0.0;
@@ -993,13 +1116,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<S
             NodeVals<A> h;
             ring_decode(h);
             node_density<A>(I, h);
-            if (in_zrange_sink(tinfo[6][t], zp)) sink_reset<A>(I, h);
-            ps.put(hi(fi), psi_of<A>(h.rho[0], I.psi_exp), psi_of<A>(h.rho[1], I.psi_exp));
+            if (in_zrange_sink(tinfo[6][t], zp)) {
+                const uint32_t hh = tinfo[1][t];
+                sink_reset<A, kExact<St>>(I, h, node_key(I, lo(hh), hi(hh), zp));
+            }
+            if (wallc) ps.put(hi(fi), Par<A>::psiw(I, 0), Par<A>::psiw(I, 1));
+            else ps.put(hi(fi), psi_of<A>(h.rho[0], I.psi_exp), psi_of<A>(h.rho[1], I.psi_exp));
         }
         node_density<A>(I, v);
-        if (own && in_zrange_sink(tinfo[4][t], zp)) fl = sink_reset<A>(I, v);
+        if (own && in_zrange_sink(tinfo[4][t], zp)) {
+            const uint32_t o = tinfo[0][t];
+            fl = sink_reset<A, kExact<St>>(I, v, node_key(I, lo(o), hi(o), zp));
+        }
         if (own) {
-            ps.put(lo(fi), psi_of<A>(v.rho[0], I.psi_exp), psi_of<A>(v.rho[1], I.psi_exp));
+            if (wallc) ps.put(lo(fi), Par<A>::psiw(I, 0), Par<A>::psiw(I, 1));
+            else ps.put(lo(fi), psi_of<A>(v.rho[0], I.psi_exp), psi_of<A>(v.rho[1], I.psi_exp));
         }
         if (book && zq >= z0 && zq < z1 && __builtin_amdgcn_ballot_w64(fl != 0.0))
             ewave = wave_uniform(ewave + block_sum_wave(fl));
@@ -1024,7 +1155,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<S
             A S[2][3];
             force_sum<A>(psiS[dz > 0 ? sb : sa], psiS[sc0], psiS[dz > 0 ? sa : sb], sc, sr, row, S);
             const Psi2<A> pc = psiS[sc0].get(fo);
-            collide_node<A>(I, v, S, pc[0], pc[1]);
+            collide_node<A, kExact<St>>(I, v, S, pc[0], pc[1], xy + (uint32_t)z * (uint32_t)I.nx * (uint32_t)I.ny);
         }
         store_node<St>(d, I, z, xy, v);
     };
@@ -1284,9 +1415,9 @@ __global__ void k_init_density(Inst I, const double* __restrict__ rhoA, const do
     }
 }
 
-// From full FP64 populations f[(c*19 + i)*n + node].
+// From full FP64 populations f[(c*19 + i)*fstride + node].
 template <class S>
-__global__ void k_init_pops(Inst I, const double* __restrict__ f, typename S::T* __restrict__ dst)
+__global__ void k_init_pops(Inst I, const double* __restrict__ f, int64_t fstride, typename S::T* __restrict__ dst)
 {
     const int64_t n = I.n;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
@@ -1308,7 +1439,8 @@ __global__ void k_init_pops(Inst I, const double* __restrict__ f, typename S::T*
                 q = i;
             }
             for (int c = 0; c < 2; ++c)
-                put_slot<S>(d, I, c, i, z, xy, f[(int64_t)(c * kQ + q) * n + src], f[(int64_t)(c * kQ) * n + k]);
+                put_slot<S>(d, I, c, i, z, xy, f[(int64_t)(c * kQ + q) * fstride + src],
+                            f[(int64_t)(c * kQ) * fstride + k]);
         }
     }
 }
@@ -1324,7 +1456,7 @@ __device__ __forceinline__ void state_at(const typename S::T* s, const Inst& I, 
     using A = typename S::A;
     pull_node<S>(s, I, x, y, z, v);
     node_density<A>(I, v);
-    if (in_sink(I.reset, x, y, z, I.nx, I.ny, I.nz)) sink_reset<A>(I, v);
+    if (in_sink(I.reset, x, y, z, I.nx, I.ny, I.nz)) sink_reset<A, kExact<S>>(I, v, node_key(I, x, y, z));
 }
 
 template <class S>
@@ -1342,8 +1474,9 @@ __global__ void k_read_density(Inst I, const typename S::T* __restrict__ src, do
     }
 }
 
+// out[(c*19 + i)*ostride + node].
 template <class S>
-__global__ void k_read_pops(Inst I, const typename S::T* __restrict__ src, double* __restrict__ out)
+__global__ void k_read_pops(Inst I, const typename S::T* __restrict__ src, double* __restrict__ out, int64_t ostride)
 {
     using A = typename S::A;
     const typename S::T* s = src + I.base;
@@ -1354,15 +1487,16 @@ __global__ void k_read_pops(Inst I, const typename S::T* __restrict__ src, doubl
         for (int c = 0; c < 2; ++c)
 #pragma unroll
             for (int i = 0; i < kQ; ++i)
-                out[(int64_t)(c * kQ + i) * I.n + k] = (double)v.f[c][i] + wgt(i) * I.shift[c];
+                out[(int64_t)(c * kQ + i) * ostride + k] = (double)v.f[c][i] + wgt(i) * I.shift[c];
     }
 }
 
 // Barycentric velocity U of Eq. (velw) from S(t) and its densities (already
-// written by k_read_density): U = (sum_c j^c + (F^A + F^B)/2) / sum_c rho^c.
+// written by k_read_density): U = (sum_c j^c + (F^A + F^B)/2) / sum_c rho^c,
+// into U[d*ustride + node].
 template <class S>
 __global__ void k_read_velocity(Inst I, const typename S::T* __restrict__ src, const double* __restrict__ rhoA,
-                                const double* __restrict__ rhoB, double* __restrict__ U)
+                                const double* __restrict__ rhoB, double* __restrict__ U, int64_t ustride)
 {
     using A = typename S::A;
     const typename S::T* s = src + I.base;
@@ -1387,7 +1521,7 @@ __global__ void k_read_velocity(Inst I, const typename S::T* __restrict__ src, c
                     const int zn = psi_plane(z + ez(i), I.nz, I.wall_z);
                     const int64_t nb = node_of(wrap(x + ex(i), I.nx), wrap(y + ey(i), I.ny), zn, I.nx, I.ny);
                     const double r = rho[1 - c][nb];
-                    const double p = I.psi_exp ? 1.0 - exp(-r) : r;
+                    const double p = beyond_wall(I, z + ez(i)) ? I.psi_w[1 - c] : (I.psi_exp ? 1.0 - exp(-r) : r);
                     Sv[0] += wgt(i) * p * ex(i);
                     Sv[1] += wgt(i) * p * ey(i);
                     Sv[2] += wgt(i) * p * ez(i);
@@ -1398,7 +1532,7 @@ __global__ void k_read_velocity(Inst I, const typename S::T* __restrict__ src, c
             }
         }
         const double rt = rhoA[k] + rhoB[k];
-        for (int dd = 0; dd < 3; ++dd) U[(int64_t)dd * I.n + k] = num[dd] / rt;
+        for (int dd = 0; dd < 3; ++dd) U[(int64_t)dd * ustride + k] = num[dd] / rt;
     }
 }
 
@@ -1446,8 +1580,10 @@ __global__ __launch_bounds__(256) void k_diag_planes(Inst I, const typename S::T
         NodeVals<A> v;
         pull_node<S>(s, I, x, y, z, v);
         node_density<A>(I, v);
-        if (in_sink(I.reset, x, y, z, I.nx, I.ny, I.nz)) acc[6] += sink_reset<A>(I, v);
-        const double ra = I.shift[0] + (double)v.drho[0], rb = I.shift[1] + (double)v.drho[1];
+        if (in_sink(I.reset, x, y, z, I.nx, I.ny, I.nz)) acc[6] += sink_reset<A, kExact<S>>(I, v, node_key(I, x, y, z));
+        // masses from the exact FP64 sums of the stored deviations (the FP32
+        // sums carry a rounding that repeats at every node of a uniform region)
+        const double ra = I.shift[0] + sum64(v.f[0]), rb = I.shift[1] + sum64(v.f[1]);
         acc[0] += ra;
         acc[1] += rb;
         for (int c = 0; c < 2; ++c)

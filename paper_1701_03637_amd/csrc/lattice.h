@@ -41,7 +41,7 @@ enum SinkKind : int32_t { kSinkNone = 0, kSinkZmax = 1, kSinkFaces = 2, kSinkSph
 
 struct Sink {
     int32_t kind;
-    int32_t pad;
+    int32_t no_zlo;   // faces sink without its z = 0 face (a solid wall lies below)
     double rho_h;     // density imposed on component A
     double r2;        // squared radius of a spherical sink
     double cx, cy, cz;
@@ -51,7 +51,8 @@ LBSC_HD bool in_sink(const Sink& s, int x, int y, int z, int nx, int ny, int nz)
 {
     switch (s.kind) {
     case kSinkZmax: return z == nz - 1;
-    case kSinkFaces: return x == 0 || y == 0 || z == 0 || x == nx - 1 || y == ny - 1 || z == nz - 1;
+    case kSinkFaces:
+        return x == 0 || y == 0 || (z == 0 && !s.no_zlo) || x == nx - 1 || y == ny - 1 || z == nz - 1;
     case kSinkSphere: {
         double dx = x - s.cx, dy = y - s.cy, dz = z - s.cz;
         return dx * dx + dy * dy + dz * dz >= s.r2;
@@ -72,8 +73,9 @@ LBSC_HD uint32_t sink_zrange(const Sink& s, int x, int y, int nx, int ny, int nz
     switch (s.kind) {
     case kSinkZmax: hi = nz - 2; break;
     case kSinkFaces:
-        lo = 1;
-        hi = (x == 0 || y == 0 || x == nx - 1 || y == ny - 1) ? 0 : nz - 2;
+        lo = s.no_zlo ? 0 : 1;
+        hi = nz - 2;
+        if (x == 0 || y == 0 || x == nx - 1 || y == ny - 1) hi = lo - 1;
         break;
     case kSinkSphere: {
         const double dx = x - s.cx, dy = y - s.cy;
@@ -102,12 +104,24 @@ LBSC_HD uint32_t sink_zrange(const Sink& s, int x, int y, int nx, int ny, int nz
     }
     default: break;
     }
+    // A column with no fluid node (a one-plane lattice under a z-max or
+    // face sink) takes the all-sink encoding.
+    if (hi < lo) {
+        lo = 1;
+        hi = 0;
+    }
     return (uint32_t)lo | ((uint32_t)hi << 16);
 }
 
 LBSC_HD bool in_zrange_sink(uint32_t zr, int z) { return z < (int)(zr & 0xffffu) || z > (int)(zr >> 16); }
 
 // Per-instance description, stored in device memory.
+// A lattice with a solid wall of h planes at its bottom is described to the
+// kernels by its fluid part alone: nz - h planes starting h slabs into the
+// instance's storage, with the seam wall on both ends (below the first fluid
+// plane and, through the periodic wrap, above the last) and psi_wall = 1, the
+// solid nodes' constant psi in place of the seam's mirror. z_off = h maps its
+// planes back to the caller's lattice.
 struct Inst {
     int32_t nx, ny, nz, wall_z;
     int32_t psi_exp;       // 0: psi = rho, 1: psi = 1 - exp(-rho)
@@ -128,6 +142,12 @@ struct Inst {
     Sink reset;            // sink that formed the stored state (applied on pull)
     Sink cur;              // current sink (its nodes skip collision)
     int32_t item_begin, item_end;   // this instance's work items
+    int32_t psi_wall;      // 1: psi beyond the wall is psi_w (solid nodes), 0: mirrored
+    int32_t z_off;         // solid planes below the kernels' lattice
+    int32_t ncomp;         // components: 2, or 1 (single-component multiphase form)
+    int32_t pad2;
+    double psi_w[2];       // psi of the solid nodes per component
+    float psi_wf[2];
 };
 
 // Arena element of population (c, i) at in-plane index xy = y*nx + x of
@@ -151,6 +171,7 @@ LBSC_HD int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
 // Plane index providing psi for a z outside [0, nz): periodic wrap, or the
 // mirror psi(-1) := psi(0), psi(nz) := psi(nz-1) at a wall on the z seam.
+// (Behind a solid wall psi is the wall's constant instead: see beyond_wall.)
 LBSC_HD int psi_plane(int z, int nz, int wall_z)
 {
     if (z >= 0 && z < nz) return z;
@@ -174,5 +195,8 @@ LBSC_HD PullSrc pull_src(int i, int x, int y, int z, int nx, int ny, int nz, int
 }
 
 LBSC_HD int64_t node_of(int x, int y, int z, int nx, int ny) { return ((int64_t)z * ny + y) * nx + x; }
+
+// Plane z lies behind a solid wall, where psi is the wall's constant.
+LBSC_HD bool beyond_wall(const Inst& I, int z) { return I.psi_wall && I.wall_z && (z < 0 || z >= I.nz); }
 
 }  // namespace lbsc

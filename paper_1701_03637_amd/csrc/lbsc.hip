@@ -8,12 +8,16 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
 #include "lbsc.h"
 #include "kernels.h"
+#include "kernels1.h"
 
 using lbsc::Inst;
 using lbsc::Item;
@@ -21,15 +25,33 @@ using lbsc::Item;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kCUs = 256;  // compute units of an MI355X
+
+// Compute units of the current device (256 on an MI355X), which the default
+// schedule fills; 256 if the query fails.
+int device_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        return 256;
+    return cus;
+}
 constexpr uint64_t kMagic = 0x4C4253432D434B31ull;  // "LBSC-CK1"
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 size_t elem_size(int prec) { return prec == LBSC_FP64 ? 8 : (prec == LBSC_FP32S ? 4 : 2); }
 
-// Slab elements per in-plane element (see kSlabPlanes in kernels.h).
-int slab_planes(int prec) { return prec == LBSC_FP16N ? 40 : 2 * lbsc::kQ; }
+// Components of an instance: 1 (single-component multiphase form) or 2.
+int ncomp_of(const lbsc_params& p) { return p.ncomp == 1 ? 1 : 2; }
+
+// Slab elements per in-plane element (see kSlabPlanes in kernels.h and
+// kSlabPlanes1 in kernels1.h).
+int slab_planes(int prec, int ncomp)
+{
+    if (ncomp == 1) return lbsc::kSlabPlanes1;
+    return prec == LBSC_FP16N ? 40 : 2 * lbsc::kQ;
+}
 
 struct CkptHeader {
     uint64_t magic;
@@ -49,8 +71,11 @@ struct lbsc_ctx {
     std::vector<Inst> inst;       // host copy of the device table
     std::vector<Item> items;
     lbsc_tiles tiles{0, 0, 0, 0, 0};
+    std::vector<lbsc_tiles> inst_tiles;   // per-instance tw, th, nzc (0: the context's)
     int nt = 256;
     int variant = 1;              // resolved k_step variant: 1 keep, 2 re-pull, 3 pipelined
+    int cus = 256;                // compute units the default schedule fills
+    int ncomp = 2;                // components of every instance
     size_t pop_elems = 0;         // elements per population buffer
     size_t max_items = 0;
     int max_nz = 0;
@@ -98,21 +123,37 @@ lbsc_status fail(lbsc_ctx* c, lbsc_status s, const char* fmt, ...)
         if (e_ != hipSuccess) return fail((ctx), LBSC_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
-lbsc::Sink make_sink(int kind, double rho_h, double radius, const double* center)
+// Sink in the kernels' coordinates: above a solid wall of z_off planes the
+// kernels' lattice starts at the caller's plane z_off, and the caller's
+// z = 0 face is solid, not a sink.
+lbsc::Sink make_sink(int kind, double rho_h, double radius, const double* center, int z_off)
 {
     lbsc::Sink s{};
     s.kind = kind;
+    s.no_zlo = z_off > 0 && kind == LBSC_SINK_FACES;
     s.rho_h = rho_h;
     s.r2 = radius * radius;
     s.cx = center[0];
     s.cy = center[1];
-    s.cz = center[2];
+    s.cz = center[2] - z_off;
     return s;
 }
 
 bool same_sink(const lbsc::Sink& a, const lbsc::Sink& b)
 {
-    return a.kind == b.kind && a.rho_h == b.rho_h && a.r2 == b.r2 && a.cx == b.cx && a.cy == b.cy && a.cz == b.cz;
+    return a.kind == b.kind && a.no_zlo == b.no_zlo && a.rho_h == b.rho_h && a.r2 == b.r2 && a.cx == b.cx &&
+           a.cy == b.cy && a.cz == b.cz;
+}
+
+// psi of Eq. (psifunc) (rho_0 = 1) or psi = rho, in FP64 on the host.
+double psi_host(int psi, double rho) { return psi == LBSC_PSI_EXP ? 1.0 - std::exp(-rho) : rho; }
+
+// FP16S with a sink needs the explicit flag: its constant-shift FP16 rounds
+// away the slow relaxation of the vapour, and the sink then books a flux
+// that never leaves the droplet.
+bool fp16s_sink_refused(int precision, int sink, int flags)
+{
+    return precision == LBSC_FP16S && sink != LBSC_SINK_NONE && !(flags & LBSC_FLAG_FP16S_SINK);
 }
 
 lbsc_status validate(const lbsc_params& p, int k, std::string& why)
@@ -125,7 +166,8 @@ lbsc_status validate(const lbsc_params& p, int k, std::string& why)
     };
     if (p.nx < 1 || p.ny < 1 || p.nz < 1 || p.nx > 4096 || p.ny > 4096 || p.nz > 4096) return bad("size out of 1..4096");
     if ((int64_t)p.nx * p.ny * p.nz >= (int64_t(1) << 31)) return bad("nx*ny*nz must be < 2^31");
-    if ((int64_t)slab_planes(p.precision) * ((int64_t)p.nx * p.ny + 64 + p.plane_pad) *
+    if (p.ncomp < 0 || p.ncomp > 2) return bad("ncomp must be 0, 1 or 2");
+    if ((int64_t)slab_planes(p.precision, ncomp_of(p)) * ((int64_t)p.nx * p.ny + 64 + p.plane_pad) *
             (int64_t)elem_size(p.precision) >= (int64_t(1) << 32))
         return bad("one z-slab of population planes must be < 4 GiB");
     if (!(p.tau[0] > 0.5) || !(p.tau[1] > 0.5)) return bad("tau must be > 0.5");
@@ -137,6 +179,19 @@ lbsc_status validate(const lbsc_params& p, int k, std::string& why)
     if (p.phi_delta[0] == p.phi_delta[1]) return bad("phi_delta[0] must differ from phi_delta[1]");
     if (!std::isfinite(p.shift[0]) || !std::isfinite(p.shift[1])) return bad("shift not finite");
     if (p.plane_pad < 0 || p.plane_pad > (1 << 20)) return bad("plane_pad out of 0..2^20");
+    if (p.flags & ~LBSC_FLAG_FP16S_SINK) return bad("unknown flag bits");
+    if (p.solid_z < 0 || p.solid_z >= p.nz) return bad("solid_z out of 0..nz-1");
+    if (p.solid_z > 0 && p.wall_z) return bad("solid_z and wall_z exclude each other");
+    if (!std::isfinite(p.wall_rho[0]) || !std::isfinite(p.wall_rho[1])) return bad("wall_rho not finite");
+    if (p.reserved != 0) return bad("reserved field must be 0");
+    if (ncomp_of(p) == 1 && p.precision != LBSC_FP64 && p.precision != LBSC_FP32S) {
+        why = "the single-component form stores FP64 or FP32S populations";
+        return LBSC_E_UNSUPPORTED;
+    }
+    if (fp16s_sink_refused(p.precision, p.sink, p.flags)) {
+        why = "FP16S storage with an evaporation sink (set LBSC_FLAG_FP16S_SINK to accept it)";
+        return LBSC_E_UNSUPPORTED;
+    }
     return LBSC_OK;
 }
 
@@ -156,7 +211,7 @@ std::vector<int> split_range(int n, int w, int parts)
 }
 
 void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int min_rows, int64_t total_nodes,
-                    int target_items, std::vector<Item>& out)
+                    int target_items, int cus, std::vector<Item>& out)
 {
     // Defaults from tile sweeps on MI355X: a tile spans the whole x extent
     // (contiguous reads, no x halo) while the block still holds min_rows rows
@@ -192,7 +247,7 @@ void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int mi
     } else {
         const double share = (double)I.n / (double)total_nodes / cols;
         const int want = std::max(1, (int)std::ceil(target_items * share));
-        const int fill = (int)std::ceil(kCUs * share);
+        const int fill = (int)std::ceil(cus * share);
         const int chunks = std::min({want, std::max({1, I.nz / 16, fill}), I.nz});
         zb = split_range(I.nz, 0, chunks);
     }
@@ -238,15 +293,25 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
     // width stays cheaper down to 3 rows for the pipelined step (2-row tiles
     // pulled twice their nodes and lost to 64 x 4 in FP64). The
     // register-keeping steps pay more per halo pull and run best on 8 rows.
-    const bool pipe_ok = !f64 || nt == 256;
+    if (c->ncomp == 1 && t.variant > 1)
+        return fail(c, LBSC_E_ARG, "the single-component step has one variant (1)");
+    const bool pipe_ok = c->ncomp == 2 && (!f64 || nt == 256);
     const int want = t.variant > 0 ? t.variant : (pipe_ok ? 3 : 1);
     const int min_rows = want == 3 ? 3 : 8;
     int64_t total = 0;
     for (auto& I : inst) total += I.n;
     items.clear();
     for (int k = 0; k < (int)inst.size(); ++k) {
+        // an instance's own tile width, rows and chunk length override the
+        // context's
+        lbsc_tiles tk = t;
+        const lbsc_tiles& o = c->inst_tiles[k];
+        if (o.tw > 0) tk.tw = o.tw;
+        if (o.th > 0) tk.th = o.th;
+        if (o.nzc > 0) tk.nzc = o.nzc;
+        if (tk.tw > 512 || tk.th > 512) return fail(c, LBSC_E_ARG, "instance %d: tw and th must be <= 512", k);
         inst[k].item_begin = (int32_t)items.size();
-        instance_items(inst[k], k, t, nt, min_rows, total, target_items, items);
+        instance_items(inst[k], k, tk, nt, min_rows, total, target_items, c->cus, items);
         inst[k].item_end = (int32_t)items.size();
     }
     if (items.size() > c->max_items)
@@ -341,8 +406,28 @@ hipError_t launch_step_p(lbsc_ctx* c, hipStream_t s, int src)
     return c->variant == 2 ? launch_step_k<St, false>(c, s, src) : launch_step_k<St, true>(c, s, src);
 }
 
+template <class St, int NT>
+hipError_t launch_step1_t(lbsc_ctx* c, hipStream_t s, int src)
+{
+    using T = typename St::T;
+    const int n = (int)c->items.size();
+    const int grid = ((n + 7) / 8) * 8;
+    hipLaunchKernelGGL((lbsc::k_step1<St, NT>), dim3(grid), dim3(NT), 0, s, c->d_inst(), c->d_items(), n,
+                       (const T*)c->pop[src], (T*)c->pop[src ^ 1], c->d_eacc());
+    return hipGetLastError();
+}
+
+template <class St>
+hipError_t launch_step1(lbsc_ctx* c, hipStream_t s, int src)
+{
+    return c->nt == 512 ? launch_step1_t<St, 512>(c, s, src) : launch_step1_t<St, 256>(c, s, src);
+}
+
 hipError_t launch_step(lbsc_ctx* c, hipStream_t s, int src)
 {
+    if (c->ncomp == 1)
+        return c->precision == LBSC_FP64 ? launch_step1<lbsc::St1F64>(c, s, src)
+                                         : launch_step1<lbsc::St1F32S>(c, s, src);
     switch (c->precision) {
     case LBSC_FP64: return launch_step_p<lbsc::StF64>(c, s, src);
     case LBSC_FP32S: return launch_step_p<lbsc::StF32S>(c, s, src);
@@ -384,6 +469,14 @@ hipError_t by_precision(int prec, F&& f)
     }
 }
 
+// Single-component storage policy of a precision (FP64 or FP32S).
+template <typename F>
+hipError_t by_precision1(int prec, F&& f)
+{
+    if (prec == LBSC_FP64) return f(lbsc::St1F64{});
+    return f(lbsc::St1F32S{});
+}
+
 lbsc_status fold_eacc(lbsc_ctx* c)
 {
     hipLaunchKernelGGL(lbsc::k_fold_eacc, dim3((c->n_inst + 63) / 64), dim3(64), 0, c->stream, c->d_inst(),
@@ -416,6 +509,58 @@ lbsc_status apply_schedule(lbsc_ctx* c, const lbsc_tiles& t)
     return LBSC_OK;
 }
 
+// Tuning cache: schedules the tuner kept, by (architecture, lattice size,
+// precision, components, context nt, context variant), for this build's
+// kernel sources (LBSC_KERNEL_HASH, a hash of their code). A one-instance
+// context stores its whole schedule under nt = variant = 0; an instance of a
+// batch its tile width, rows and chunk length under the batch's nt and
+// variant.
+#ifndef LBSC_KERNEL_HASH
+#define LBSC_KERNEL_HASH "unknown"
+#endif
+using TuneKey = std::tuple<std::string, int, int, int, int, int, int, int>;
+std::map<TuneKey, lbsc_tiles> g_tune_cache;
+std::mutex g_tune_mutex;
+
+std::string device_arch()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+TuneKey tune_key(const lbsc_ctx* c, int inst, int nt, int variant, const std::string& arch)
+{
+    const lbsc_params& p = c->params[inst];
+    return TuneKey{arch, p.nx, p.ny, p.nz, c->precision, c->ncomp, nt, variant};
+}
+
+bool cache_get(const TuneKey& k, lbsc_tiles& out)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    auto it = g_tune_cache.find(k);
+    if (it == g_tune_cache.end()) return false;
+    out = it->second;
+    return true;
+}
+
+void cache_put(const TuneKey& k, const lbsc_tiles& t)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_cache[k] = t;
+}
+
+// Size class of an instance for the tuner's per-instance pass: boxes of
+// similar width take the same tile shapes.
+int size_class(const lbsc_params& p)
+{
+    const int w = std::max(p.nx, p.ny);
+    return w < 64 ? 0 : (w < 96 ? 1 : (w < 128 ? 2 : (w < 192 ? 3 : 4)));
+}
+
 }  // namespace
 
 extern "C" {
@@ -443,10 +588,13 @@ lbsc_status lbsc_create(int32_t n_inst, const lbsc_params* params, lbsc_ctx** ou
     *out = nullptr;
     for (int k = 0; k < n_inst; ++k) {
         std::string why;
-        if (validate(params[k], k, why)) return LBSC_E_ARG;
+        if (lbsc_status st = validate(params[k], k, why)) return st;
         if (params[k].precision != params[0].precision) return LBSC_E_ARG;
+        if (ncomp_of(params[k]) != ncomp_of(params[0])) return LBSC_E_ARG;
     }
     lbsc_ctx* c = new lbsc_ctx();
+    c->cus = device_cus();
+    c->ncomp = ncomp_of(params[0]);
     c->n_inst = n_inst;
     c->precision = params[0].precision;
     c->elem = elem_size(c->precision);
@@ -456,13 +604,23 @@ lbsc_status lbsc_create(int32_t n_inst, const lbsc_params* params, lbsc_ctx** ou
     for (int k = 0; k < n_inst; ++k) {
         const lbsc_params& p = params[k];
         Inst I{};
-        I.nx = p.nx; I.ny = p.ny; I.nz = p.nz; I.wall_z = p.wall_z ? 1 : 0;
+        // a solid wall of h planes: the kernels see the fluid planes above it,
+        // bounded by the seam wall on both ends (see Inst)
+        const int h = p.solid_z;
+        I.nx = p.nx; I.ny = p.ny; I.nz = p.nz - h; I.wall_z = (p.wall_z || h > 0) ? 1 : 0;
+        I.z_off = h;
+        I.psi_wall = h > 0;
+        for (int cc = 0; cc < 2; ++cc) {
+            I.psi_w[cc] = h > 0 ? psi_host(p.psi, p.wall_rho[cc]) : 0.0;
+            I.psi_wf[cc] = (float)I.psi_w[cc];
+        }
         I.psi_exp = p.psi == LBSC_PSI_EXP;
         I.count_reset = 0;
-        I.n = (int64_t)p.nx * p.ny * p.nz;
+        I.n = (int64_t)p.nx * p.ny * I.nz;
         I.ps = (int64_t)align_up((size_t)p.nx * p.ny, 64) + (int64_t)align_up((size_t)p.plane_pad, 64);
-        I.slab = slab_planes(p.precision) * I.ps;
-        I.base = (int64_t)off;
+        I.slab = slab_planes(p.precision, ncomp_of(p)) * I.ps;
+        I.ncomp = ncomp_of(p);
+        I.base = (int64_t)off + (int64_t)h * I.slab;
         off = align_up(off + (size_t)p.nz * (size_t)I.slab, 256);
         I.tau[0] = p.tau[0]; I.tau[1] = p.tau[1];
         I.omega[0] = 1.0 / p.tau[0]; I.omega[1] = 1.0 / p.tau[1];
@@ -476,13 +634,14 @@ lbsc_status lbsc_create(int32_t n_inst, const lbsc_params* params, lbsc_ctx** ou
             const float tf = (float)I.tau[cc], gf = (float)I.g;
             I.ntg_f[cc] = -tf * gf;
         }
-        I.reset = make_sink(p.sink, p.rho_h, p.sink_radius, p.center);
+        I.reset = make_sink(p.sink, p.rho_h, p.sink_radius, p.center, h);
         I.cur = I.reset;
         c->inst.push_back(I);
         total_nodes += I.n;
-        c->max_nz = std::max(c->max_nz, p.nz);
+        c->max_nz = std::max(c->max_nz, I.nz);
     }
     c->pop_elems = off;
+    c->inst_tiles.assign(n_inst, lbsc_tiles{0, 0, 0, 0, 0});
     // Bound on work items: any schedule with tiles of >= 16 nodes per plane.
     c->max_items = std::max<size_t>(65536, (size_t)(total_nodes / 16) + 64 * (size_t)n_inst);
     size_t o = 0;
@@ -526,29 +685,58 @@ lbsc_status lbsc_set_stream(lbsc_ctx* ctx, void* hip_stream)
     return LBSC_OK;
 }
 
-lbsc_status lbsc_bind(lbsc_ctx* c, void* pop0, void* pop1, void* scratch)
+static lbsc_status bind_buffers(lbsc_ctx* c, void* pop0, void* pop1, void* work)
 {
-    if (!c) return LBSC_E_ARG;
-    if (!pop0 || !pop1 || !scratch || pop0 == pop1)
+    if (!pop0 || !pop1 || !work || pop0 == pop1)
         return fail(c, LBSC_E_ARG, "bind: need two distinct population buffers and a scratch buffer");
-    if (((uintptr_t)pop0 | (uintptr_t)pop1 | (uintptr_t)scratch) % kAlign)
+    if (((uintptr_t)pop0 | (uintptr_t)pop1 | (uintptr_t)work) % kAlign)
         return fail(c, LBSC_E_ARG, "bind: buffers must be %zu-byte aligned", kAlign);
     c->pop[0] = pop0;
     c->pop[1] = pop1;
-    c->scratch = (char*)scratch;
+    c->scratch = (char*)work;
     c->bound = true;
     c->cur = 0;
     drop_graphs(c);
-    const int64_t nacc = (int64_t)(c->max_items + c->n_inst);
+    // the accumulators start at zero (fill kernels: no memset nodes in
+    // anything a caller may capture)
     hipLaunchKernelGGL(lbsc::k_fill_f64, dim3(fill_grid(c->max_items)), dim3(256), 0, c->stream, c->d_eacc(),
                        (int64_t)c->max_items, 0.0);
     HIPCHK(c, hipGetLastError());
     hipLaunchKernelGGL(lbsc::k_fill_f64, dim3(1), dim3(256), 0, c->stream, c->d_ebase(), (int64_t)c->n_inst, 0.0);
     HIPCHK(c, hipGetLastError());
-    (void)nacc;
     lbsc_status s = upload_items(c);
     if (s) return s;
     return upload_table(c);
+}
+
+lbsc_status lbsc_bind(lbsc_ctx* c, void* pop0, void* pop1, void* work)
+{
+    if (!c) return LBSC_E_ARG;
+    return bind_buffers(c, pop0, pop1, work);
+}
+
+// Nodes of the caller's lattice of instance inst (solid planes included),
+// and the offset of the kernels' first node in the caller's arrays.
+static int64_t user_nodes(const lbsc_ctx* c, int inst)
+{
+    const lbsc_params& p = c->params[inst];
+    return (int64_t)p.nx * p.ny * p.nz;
+}
+static int64_t solid_nodes(const lbsc_ctx* c, int inst)
+{
+    const lbsc_params& p = c->params[inst];
+    return (int64_t)p.nx * p.ny * p.solid_z;
+}
+
+// Zeros over the solid planes of `planes` caller arrays of user_nodes each.
+static lbsc_status zero_solid(lbsc_ctx* c, int inst, double* out, int planes)
+{
+    const int64_t ns = solid_nodes(c, inst), nu = user_nodes(c, inst);
+    for (int q = 0; q < planes && ns > 0; ++q) {
+        hipLaunchKernelGGL(lbsc::k_fill_f64, dim3(fill_grid(ns)), dim3(256), 0, c->stream, out + q * nu, ns, 0.0);
+        HIPCHK(c, hipGetLastError());
+    }
+    return LBSC_OK;
 }
 
 static lbsc_status begin_init(lbsc_ctx* c, int inst)
@@ -575,13 +763,24 @@ lbsc_status lbsc_init_from_density(lbsc_ctx* c, int32_t inst, const double* rhoA
 {
     lbsc_status s = begin_init(c, inst);
     if (s) return s;
-    if (!rhoA || !rhoB) return fail(c, LBSC_E_ARG, "init: null density pointer");
+    if (!rhoA || (!rhoB && c->ncomp == 2)) return fail(c, LBSC_E_ARG, "init: null density pointer");
     const Inst I = c->inst[inst];
+    const int64_t off = solid_nodes(c, inst);  // solid nodes hold no fluid
+    if (c->ncomp == 1) {
+        HIPCHK(c, by_precision1(c->precision, [&](auto tag) {
+                   using S = decltype(tag);
+                   using T = typename S::T;
+                   hipLaunchKernelGGL(lbsc::k_init_density1<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
+                                      rhoA + off, (T*)c->pop[c->cur]);
+                   return hipGetLastError();
+               }));
+        return upload_table(c);
+    }
     HIPCHK(c, by_precision(c->precision, [&](auto tag) {
                using S = decltype(tag);
                using T = typename S::T;
-               hipLaunchKernelGGL(lbsc::k_init_density<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I, rhoA,
-                                  rhoB, (T*)c->pop[c->cur]);
+               hipLaunchKernelGGL(lbsc::k_init_density<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
+                                  rhoA + off, rhoB + off, (T*)c->pop[c->cur]);
                return hipGetLastError();
            }));
     return upload_table(c);
@@ -593,11 +792,22 @@ lbsc_status lbsc_init_from_populations(lbsc_ctx* c, int32_t inst, const double* 
     if (s) return s;
     if (!f) return fail(c, LBSC_E_ARG, "init: null population pointer");
     const Inst I = c->inst[inst];
+    const int64_t off = solid_nodes(c, inst), nu = user_nodes(c, inst);
+    if (c->ncomp == 1) {
+        HIPCHK(c, by_precision1(c->precision, [&](auto tag) {
+                   using S = decltype(tag);
+                   using T = typename S::T;
+                   hipLaunchKernelGGL(lbsc::k_init_pops1<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
+                                      f + off, nu, (T*)c->pop[c->cur]);
+                   return hipGetLastError();
+               }));
+        return upload_table(c);
+    }
     HIPCHK(c, by_precision(c->precision, [&](auto tag) {
                using S = decltype(tag);
                using T = typename S::T;
-               hipLaunchKernelGGL(lbsc::k_init_pops<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I, f,
-                                  (T*)c->pop[c->cur]);
+               hipLaunchKernelGGL(lbsc::k_init_pops<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I, f + off,
+                                  nu, (T*)c->pop[c->cur]);
                return hipGetLastError();
            }));
     return upload_table(c);
@@ -609,10 +819,13 @@ lbsc_status lbsc_set_sink(lbsc_ctx* c, int32_t inst, int32_t kind, double rho_h,
     if (s) return s;
     if (kind < LBSC_SINK_NONE || kind > LBSC_SINK_SPHERE || !std::isfinite(rho_h) || !std::isfinite(radius))
         return fail(c, LBSC_E_ARG, "set_sink: bad kind or value");
+    if (fp16s_sink_refused(c->precision, kind, c->params[inst].flags))
+        return fail(c, LBSC_E_UNSUPPORTED,
+                    "set_sink: FP16S storage with an evaporation sink (create with LBSC_FLAG_FP16S_SINK to accept it)");
     c->params[inst].sink = kind;
     c->params[inst].rho_h = rho_h;
     c->params[inst].sink_radius = radius;
-    c->inst[inst].cur = make_sink(kind, rho_h, radius, c->params[inst].center);
+    c->inst[inst].cur = make_sink(kind, rho_h, radius, c->params[inst].center, c->inst[inst].z_off);
     return upload_table(c);
 }
 
@@ -702,11 +915,53 @@ lbsc_status lbsc_num_items(const lbsc_ctx* c, int32_t* n)
     return LBSC_OK;
 }
 
+lbsc_status lbsc_set_inst_tiles(lbsc_ctx* c, int32_t inst, const lbsc_tiles* t)
+{
+    if (!c || !t) return LBSC_E_ARG;
+    if (inst < 0 || inst >= c->n_inst) return fail(c, LBSC_E_ARG, "instance %d out of range", inst);
+    if (t->tw < 0 || t->th < 0 || t->nzc < 0 || t->tw > 512 || t->th > 512)
+        return fail(c, LBSC_E_ARG, "set_inst_tiles: tw, th in 0..512 and nzc >= 0");
+    const lbsc_tiles old = c->inst_tiles[inst];
+    c->inst_tiles[inst] = lbsc_tiles{0, t->tw, t->th, t->nzc, 0};
+    lbsc_status s = apply_schedule(c, c->tiles);
+    if (s) {
+        c->inst_tiles[inst] = old;
+        (void)apply_schedule(c, c->tiles);
+    }
+    return s;
+}
+
+lbsc_status lbsc_get_inst_tiles(const lbsc_ctx* c, int32_t inst, lbsc_tiles* out)
+{
+    if (!c || !out || inst < 0 || inst >= c->n_inst) return LBSC_E_ARG;
+    *out = c->inst_tiles[inst];
+    out->nt = c->nt;
+    out->variant = c->variant;
+    return LBSC_OK;
+}
+
 lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
 {
     lbsc_status s = check_bound(c);
     if (s) return s;
     if (steps < 2) return fail(c, LBSC_E_ARG, "tune: steps must be >= 2");
+    const std::string arch = device_arch();
+    auto report = [&]() {
+        if (chosen) {
+            *chosen = c->tiles;
+            chosen->nt = c->nt;
+            chosen->variant = c->variant;
+        }
+    };
+    // A one-instance context tuned before on this architecture and build
+    // takes its schedule from the cache.
+    if (c->n_inst == 1) {
+        lbsc_tiles t;
+        if (cache_get(tune_key(c, 0, 0, 0, arch), t) && apply_schedule(c, t) == LBSC_OK) {
+            report();
+            return LBSC_OK;
+        }
+    }
     std::vector<lbsc_tiles> cands;
     // Chunks of 1-4 planes are timed only on lattices below 2^22 nodes, where
     // 16-plane chunks of 512-node tiles give fewer than two blocks per CU and
@@ -729,11 +984,8 @@ lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
     const lbsc_tiles before = c->tiles;
     const int graph_before = c->graph_steps;
     c->graph_steps = 0;
-    // Time of `n` steps of schedule t after a 2-step warm-up; negative if
-    // the schedule does not apply.
-    auto time_schedule = [&](const lbsc_tiles& t, int n, float& ms) -> lbsc_status {
-        ms = -1.f;
-        if (apply_schedule(c, t) != LBSC_OK) return LBSC_OK;
+    // Time of `n` steps of the schedule in place after a 2-step warm-up.
+    auto time_current = [&](int n, float& ms) -> lbsc_status {
         lbsc_status st = lbsc_step(c, 2);
         if (st) return st;
         HIPCHK(c, hipEventRecord(e0, c->stream));
@@ -742,6 +994,12 @@ lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
         HIPCHK(c, hipEventSynchronize(e1));
         HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
         return LBSC_OK;
+    };
+    // As above for schedule t; negative if the schedule does not apply.
+    auto time_schedule = [&](const lbsc_tiles& t, int n, float& ms) -> lbsc_status {
+        ms = -1.f;
+        if (apply_schedule(c, t) != LBSC_OK) return LBSC_OK;
+        return time_current(n, ms);
     };
     std::vector<std::pair<float, lbsc_tiles>> timed;
     std::vector<std::string> seen;
@@ -772,53 +1030,190 @@ lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
             }
         }
     }
+    if (!s) s = apply_schedule(c, best_t);
+    // Per-instance pass (batches): for each size class in turn, the class's
+    // tile width and chunk length that make the whole batch's step fastest,
+    // the other instances kept as they are; cached per instance size.
+    if (!s && c->n_inst > 1) {
+        std::map<int, std::vector<int>> classes;
+        for (int k = 0; k < c->n_inst; ++k) classes[size_class(c->params[k])].push_back(k);
+        for (auto& kv : classes) {
+            const std::vector<int>& members = kv.second;
+            bool cached = true;
+            std::vector<lbsc_tiles> from_cache(members.size());
+            for (size_t q = 0; q < members.size(); ++q)
+                cached = cached && cache_get(tune_key(c, members[q], c->nt, c->variant, arch), from_cache[q]);
+            if (cached) {
+                for (size_t q = 0; q < members.size(); ++q) c->inst_tiles[members[q]] = from_cache[q];
+                if ((s = apply_schedule(c, c->tiles))) break;
+                continue;
+            }
+            std::vector<std::pair<float, lbsc_tiles>> ctimed;
+            for (int tw : {0, 32, 64, 128})
+                for (int nzc : {0, 8, 16, 32}) {
+                    const lbsc_tiles o{0, tw, 0, nzc, 0};
+                    for (int k : members) c->inst_tiles[k] = o;
+                    if (apply_schedule(c, c->tiles) != LBSC_OK) continue;
+                    float ms;
+                    if ((s = time_current(steps, ms))) break;
+                    ctimed.push_back({ms, o});
+                }
+            if (s) break;
+            std::stable_sort(ctimed.begin(), ctimed.end(),
+                             [](const auto& a, const auto& b) { return a.first < b.first; });
+            float cbest = 1e30f;
+            lbsc_tiles cbest_t{0, 0, 0, 0, 0};
+            for (size_t q = 0; q < std::min<size_t>(3, ctimed.size()); ++q) {
+                for (int k : members) c->inst_tiles[k] = ctimed[q].second;
+                if (apply_schedule(c, c->tiles) != LBSC_OK) continue;
+                float ms;
+                if ((s = time_current(3 * steps, ms))) break;
+                if (ms < cbest) {
+                    cbest = ms;
+                    cbest_t = ctimed[q].second;
+                }
+            }
+            if (s) break;
+            for (int k : members) {
+                c->inst_tiles[k] = cbest_t;
+                cache_put(tune_key(c, k, c->nt, c->variant, arch), cbest_t);
+            }
+            if ((s = apply_schedule(c, c->tiles))) break;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (s) return s;
     c->graph_steps = graph_before;
-    if ((s = apply_schedule(c, best_t))) return s;
-    if (chosen) {
-        *chosen = best_t;
-        chosen->nt = c->nt;
-        chosen->variant = c->variant;
+    if ((s = apply_schedule(c, c->tiles))) return s;
+    if (c->n_inst == 1) {
+        lbsc_tiles t = c->tiles;
+        t.nt = c->nt;
+        t.variant = c->variant;
+        cache_put(tune_key(c, 0, 0, 0, arch), t);
     }
+    report();
     return LBSC_OK;
 }
+
+lbsc_status lbsc_tune_cache_save(const char* path)
+{
+    if (!path) return LBSC_E_ARG;
+    FILE* f = fopen(path, "w");
+    if (!f) return LBSC_E_ARG;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    for (const auto& kv : g_tune_cache) {
+        const TuneKey& k = kv.first;
+        const lbsc_tiles& t = kv.second;
+        fprintf(f, "lbsc-tune 1 %s %s %d %d %d %d %d %d %d %d %d %d %d %d\n", LBSC_KERNEL_HASH,
+                std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
+                std::get<5>(k), std::get<6>(k), std::get<7>(k), t.nt, t.tw, t.th, t.nzc, t.variant);
+    }
+    return fclose(f) == 0 ? LBSC_OK : LBSC_E_ARG;
+}
+
+lbsc_status lbsc_tune_cache_load(const char* path, int32_t* n_loaded)
+{
+    if (!path) return LBSC_E_ARG;
+    FILE* f = fopen(path, "r");
+    if (!f) return LBSC_E_ARG;
+    char hash[65], arch[65];
+    int v[13], ver, n = 0;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    while (fscanf(f, " lbsc-tune %d %64s %64s %d %d %d %d %d %d %d %d %d %d %d %d", &ver, hash, arch, &v[0], &v[1],
+                  &v[2], &v[3], &v[4], &v[5], &v[6], &v[7], &v[8], &v[9], &v[10], &v[11]) == 15) {
+        // entries of other kernel sources describe other code: skipped
+        if (ver != 1 || strcmp(hash, LBSC_KERNEL_HASH) != 0) continue;
+        g_tune_cache[TuneKey{arch, v[0], v[1], v[2], v[3], v[4], v[5], v[6]}] =
+            lbsc_tiles{v[7], v[8], v[9], v[10], v[11]};
+        ++n;
+    }
+    fclose(f);
+    if (n_loaded) *n_loaded = n;
+    return LBSC_OK;
+}
+
+void lbsc_tune_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_cache.clear();
+}
+
+const char* lbsc_kernel_hash(void) { return LBSC_KERNEL_HASH; }
 
 lbsc_status lbsc_read_density(lbsc_ctx* c, int32_t inst, int32_t comp, double* out)
 {
     lbsc_status s = check_inst(c, inst);
     if (s) return s;
-    if (!out || comp < 0 || comp > 1) return fail(c, LBSC_E_ARG, "read_density: bad component or pointer");
+    if (!out || comp < 0 || comp >= c->ncomp) return fail(c, LBSC_E_ARG, "read_density: bad component or pointer");
     const Inst I = c->inst[inst];
+    const int64_t off = solid_nodes(c, inst);
+    if (c->ncomp == 1) {
+        HIPCHK(c, by_precision1(c->precision, [&](auto tag) {
+                   using S = decltype(tag);
+                   using T = typename S::T;
+                   hipLaunchKernelGGL(lbsc::k_read_density1<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
+                                      (const T*)c->pop[c->cur], out + off);
+                   return hipGetLastError();
+               }));
+        return zero_solid(c, inst, out, 1);
+    }
     HIPCHK(c, by_precision(c->precision, [&](auto tag) {
                using S = decltype(tag);
                using T = typename S::T;
                hipLaunchKernelGGL(lbsc::k_read_density<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
-                                  (const T*)c->pop[c->cur], comp == 0 ? out : nullptr, comp == 1 ? out : nullptr);
+                                  (const T*)c->pop[c->cur], comp == 0 ? out + off : nullptr,
+                                  comp == 1 ? out + off : nullptr);
                return hipGetLastError();
            }));
-    return LBSC_OK;
+    return zero_solid(c, inst, out, 1);
 }
 
 lbsc_status lbsc_read_observables(lbsc_ctx* c, int32_t inst, double* ra, double* rb, double* u)
 {
     lbsc_status s = check_inst(c, inst);
     if (s) return s;
-    if (u && (!ra || !rb)) return fail(c, LBSC_E_ARG, "read_observables: velocity needs both density arrays");
+    if (u && (!ra || (!rb && c->ncomp == 2)))
+        return fail(c, LBSC_E_ARG, "read_observables: velocity needs the density arrays");
     const Inst I = c->inst[inst];
+    const int64_t off = solid_nodes(c, inst), nu = user_nodes(c, inst);
+    if (c->ncomp == 1) {
+        HIPCHK(c, by_precision1(c->precision, [&](auto tag) {
+                   using S = decltype(tag);
+                   using T = typename S::T;
+                   if (ra)
+                       hipLaunchKernelGGL(lbsc::k_read_density1<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream,
+                                          I, (const T*)c->pop[c->cur], ra + off);
+                   hipError_t e = hipGetLastError();
+                   if (e != hipSuccess || !u) return e;
+                   hipLaunchKernelGGL(lbsc::k_read_velocity1<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
+                                      (const T*)c->pop[c->cur], (const double*)ra + off, u + off, nu);
+                   return hipGetLastError();
+               }));
+        if (ra && (s = zero_solid(c, inst, ra, 1))) return s;
+        if (rb) {  // no second component
+            hipLaunchKernelGGL(lbsc::k_fill_f64, dim3(fill_grid(nu)), dim3(256), 0, c->stream, rb, nu, 0.0);
+            HIPCHK(c, hipGetLastError());
+        }
+        if (u && (s = zero_solid(c, inst, u, 3))) return s;
+        return LBSC_OK;
+    }
     HIPCHK(c, by_precision(c->precision, [&](auto tag) {
                using S = decltype(tag);
                using T = typename S::T;
                if (ra || rb)
                    hipLaunchKernelGGL(lbsc::k_read_density<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
-                                      (const T*)c->pop[c->cur], ra, rb);
+                                      (const T*)c->pop[c->cur], ra ? ra + off : nullptr, rb ? rb + off : nullptr);
                hipError_t e = hipGetLastError();
                if (e != hipSuccess || !u) return e;
                hipLaunchKernelGGL(lbsc::k_read_velocity<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
-                                  (const T*)c->pop[c->cur], (const double*)ra, (const double*)rb, u);
+                                  (const T*)c->pop[c->cur], (const double*)ra + off, (const double*)rb + off, u + off,
+                                  nu);
                return hipGetLastError();
            }));
+    if (ra && (s = zero_solid(c, inst, ra, 1))) return s;
+    if (rb && (s = zero_solid(c, inst, rb, 1))) return s;
+    if (u && (s = zero_solid(c, inst, u, 3))) return s;
     return LBSC_OK;
 }
 
@@ -828,14 +1223,25 @@ lbsc_status lbsc_read_populations(lbsc_ctx* c, int32_t inst, double* f)
     if (s) return s;
     if (!f) return fail(c, LBSC_E_ARG, "read_populations: null pointer");
     const Inst I = c->inst[inst];
+    const int64_t off = solid_nodes(c, inst), nu = user_nodes(c, inst);
+    if (c->ncomp == 1) {
+        HIPCHK(c, by_precision1(c->precision, [&](auto tag) {
+                   using S = decltype(tag);
+                   using T = typename S::T;
+                   hipLaunchKernelGGL(lbsc::k_read_pops1<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
+                                      (const T*)c->pop[c->cur], f + off, nu);
+                   return hipGetLastError();
+               }));
+        return zero_solid(c, inst, f, lbsc::kQ);
+    }
     HIPCHK(c, by_precision(c->precision, [&](auto tag) {
                using S = decltype(tag);
                using T = typename S::T;
                hipLaunchKernelGGL(lbsc::k_read_pops<S>, dim3(fill_grid(I.n)), dim3(256), 0, c->stream, I,
-                                  (const T*)c->pop[c->cur], f);
+                                  (const T*)c->pop[c->cur], f + off, nu);
                return hipGetLastError();
            }));
-    return LBSC_OK;
+    return zero_solid(c, inst, f, 2 * lbsc::kQ);
 }
 
 lbsc_status lbsc_diagnostics(lbsc_ctx* c, int32_t inst, lbsc_diag* out)
@@ -844,13 +1250,22 @@ lbsc_status lbsc_diagnostics(lbsc_ctx* c, int32_t inst, lbsc_diag* out)
     if (s) return s;
     if (!out) return fail(c, LBSC_E_ARG, "diagnostics: null output");
     const Inst I = c->inst[inst];
-    HIPCHK(c, by_precision(c->precision, [&](auto tag) {
-               using S = decltype(tag);
-               using T = typename S::T;
-               hipLaunchKernelGGL(lbsc::k_diag_planes<S>, dim3(I.nz), dim3(256), 0, c->stream, I,
-                                  (const T*)c->pop[c->cur], c->d_part());
-               return hipGetLastError();
-           }));
+    if (c->ncomp == 1)
+        HIPCHK(c, by_precision1(c->precision, [&](auto tag) {
+                   using S = decltype(tag);
+                   using T = typename S::T;
+                   hipLaunchKernelGGL(lbsc::k_diag_planes1<S>, dim3(I.nz), dim3(256), 0, c->stream, I,
+                                      (const T*)c->pop[c->cur], c->d_part());
+                   return hipGetLastError();
+               }));
+    else
+        HIPCHK(c, by_precision(c->precision, [&](auto tag) {
+                   using S = decltype(tag);
+                   using T = typename S::T;
+                   hipLaunchKernelGGL(lbsc::k_diag_planes<S>, dim3(I.nz), dim3(256), 0, c->stream, I,
+                                      (const T*)c->pop[c->cur], c->d_part());
+                   return hipGetLastError();
+               }));
     hipLaunchKernelGGL(lbsc::k_diag_final<256>, dim3(1), dim3(256), 0, c->stream, I, (const double*)c->d_part(),
                        (const double*)c->d_eacc(), (const double*)c->d_ebase(), inst, c->d_out());
     HIPCHK(c, hipGetLastError());
@@ -859,7 +1274,9 @@ lbsc_status lbsc_diagnostics(lbsc_ctx* c, int32_t inst, lbsc_diag* out)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     out->step = c->step;
     out->mass[0] = h[0];
-    out->mass[1] = h[1];
+    // one component: the second plane slot held the phase midpoint (for the
+    // interface), not a mass
+    out->mass[1] = c->ncomp == 1 ? 0.0 : h[1];
     out->momentum[0] = h[2];
     out->momentum[1] = h[3];
     out->momentum[2] = h[4];
@@ -868,7 +1285,7 @@ lbsc_status lbsc_diagnostics(lbsc_ctx* c, int32_t inst, lbsc_diag* out)
     out->evaporated = h[9] + (I.count_reset ? h[6] : 0.0);
     out->nonfinite = (int64_t)h[7];
     out->nonpositive = (int64_t)h[8];
-    out->z_interface = h[10];
+    out->z_interface = h[10] + I.z_off;  // the caller's plane index
     if (out->nonfinite > 0) return fail(c, LBSC_E_NONFINITE, "instance %d: %lld nodes with non-finite density", inst,
                                         (long long)out->nonfinite);
     return LBSC_OK;
@@ -1080,14 +1497,16 @@ int32_t lbsc_selftest(void)
     {
         uint64_t st = 0x9E3779B97F4A7C15ull;
         auto rnd = [&]() {
-            st = st * 6364136223846793005ull + 1442695040888963407ull;
+            st = st * 6364136223846793005ull + 1442695040888963407ull;   // Knuth's MMIX LCG
             return (double)(st >> 11) * (1.0 / 9007199254740992.0);
         };
-        const int dims2[][3] = {{13, 11, 17}, {7, 9, 40}, {5, 5, 3}, {1, 1, 9}};
+        const int dims2[][3] = {{13, 11, 17}, {7, 9, 40}, {5, 5, 3}, {1, 1, 9}, {3, 3, 1}, {2, 2, 2}, {1, 1, 1}};
         for (auto& d : dims2)
             for (int trial = 0; trial < 60; ++trial) {
                 Sink sk{};
-                sk.kind = trial < 3 ? trial : kSinkSphere;
+                // none, z-max, faces, faces without the z = 0 face, spheres
+                sk.kind = trial < 4 ? (trial == 3 ? kSinkFaces : trial) : kSinkSphere;
+                sk.no_zlo = trial == 3;
                 const int mode = trial % 4;
                 auto coord = [&](int n) {
                     const double u = rnd() * (n + 6) - 3;
@@ -1104,6 +1523,48 @@ int32_t lbsc_selftest(void)
                     }
             }
     }
+    // Stochastic rounding of the rest population: always one of the two FP32
+    // neighbours of x (x itself when representable), and unbiased: over
+    // 2^16 keys the mean of the rounded values is x to within the sampling
+    // error of a two-point draw across one FP32 gap.
+    {
+        uint64_t st = 0x0123456789ABCDEFull;
+        auto rnd = [&]() {
+            st = st * 6364136223846793005ull + 1442695040888963407ull;   // Knuth's MMIX LCG
+            return (double)(st >> 11) * (1.0 / 9007199254740992.0);
+        };
+        for (int trial = 0; trial < 64; ++trial) {
+            const double mag = std::ldexp(1.0, -(int)(rnd() * 30));
+            const double x = (rnd() - 0.5) * mag;
+            const float f = (float)x;
+            const float lo = f <= x ? f : std::nextafter(f, -INFINITY);
+            const float hi = f >= x ? f : std::nextafter(f, INFINITY);
+            double sum = 0.0;
+            const int n = 1 << 16;
+            for (int k = 0; k < n; ++k) {
+                const float r = round_sr(x, (uint32_t)k * 2654435761u + (uint32_t)trial);
+                if (r != lo && r != hi) ++bad;
+                sum += (double)r;
+            }
+            const double gap = (double)hi - (double)lo;
+            if (std::fabs(sum / n - x) > 5.0 * 0.5 * gap / std::sqrt((double)n) + 1e-300) ++bad;
+            if ((double)f == x && round_sr(x, 7u) != f) ++bad;
+            // the same for the sum of two FP32 values, rounded through TwoSum
+            const float a = (float)(x * (0.5 + rnd())), b = (float)(x - (double)a);
+            const double xe = (double)a + (double)b;
+            const float fe = (float)xe;
+            const float lo2 = fe <= xe ? fe : std::nextafter(fe, -INFINITY);
+            const float hi2 = fe >= xe ? fe : std::nextafter(fe, INFINITY);
+            double sum2 = 0.0;
+            for (int k = 0; k < n; ++k) {
+                const float r = round_sr_sum(a, b, (uint32_t)k * 2654435761u + (uint32_t)trial);
+                if (r != lo2 && r != hi2) ++bad;
+                sum2 += (double)r;
+            }
+            const double gap2 = (double)hi2 - (double)lo2;
+            if (std::fabs(sum2 / n - xe) > 5.0 * 0.5 * gap2 / std::sqrt((double)n) + 1e-300) ++bad;
+        }
+    }
     // Work items tile every lattice exactly once.
     const int dims[][3] = {{4, 4, 128}, {128, 128, 128}, {48, 48, 48}, {156, 156, 156}, {1, 1, 64}, {200, 7, 9},
                            {4096, 2, 3}, {3, 4096, 2}, {2, 3, 4096}, {1, 1, 4096}};
@@ -1117,7 +1578,7 @@ int32_t lbsc_selftest(void)
                     I.nx = d[0]; I.ny = d[1]; I.nz = d[2];
                     I.n = (int64_t)d[0] * d[1] * d[2];
                     std::vector<Item> items;
-                    instance_items(I, 0, lbsc_tiles{nt, tw, 0, nzc, 0}, nt, min_rows, I.n, target, items);
+                    instance_items(I, 0, lbsc_tiles{nt, tw, 0, nzc, 0}, nt, min_rows, I.n, target, 256, items);
                     std::vector<unsigned char> cover((size_t)I.n, 0);
                     for (auto& it : items) {
                         if (it.tw * it.th > nt) ++bad;

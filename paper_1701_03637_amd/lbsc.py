@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbsc.so")
 
 FP64, FP32S, FP16S, FP16N = 0, 1, 2, 3
+FLAG_FP16S_SINK = 1
 PSI_RHO, PSI_EXP = 0, 1
 SINK_NONE, SINK_ZMAX, SINK_FACES, SINK_SPHERE = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32s": FP32S, "fp16s": FP16S, "fp16n": FP16N}
@@ -45,6 +46,11 @@ class Params(ctypes.Structure):
         ("sink_radius", ctypes.c_double),
         ("center", ctypes.c_double * 3),
         ("phi_delta", ctypes.c_double * 2),
+        ("solid_z", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+        ("wall_rho", ctypes.c_double * 2),
+        ("ncomp", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -73,7 +79,8 @@ SYMBOLS = [
     "lbsc_init_from_populations", "lbsc_set_sink", "lbsc_step", "lbsc_set_graph", "lbsc_set_tiles", "lbsc_get_tiles",
     "lbsc_tune", "lbsc_num_items", "lbsc_read_density", "lbsc_read_observables", "lbsc_read_populations",
     "lbsc_diagnostics", "lbsc_checkpoint_bytes", "lbsc_save", "lbsc_load", "lbsc_selftest",
-    "lbsc_stream_copy",
+    "lbsc_stream_copy", "lbsc_set_inst_tiles", "lbsc_get_inst_tiles", "lbsc_tune_cache_save",
+    "lbsc_tune_cache_load", "lbsc_tune_cache_clear", "lbsc_kernel_hash",
 ]
 
 _lib = None
@@ -116,6 +123,12 @@ def load_library():
         "lbsc_load": (i32, [vp, vp]),
         "lbsc_selftest": (i32, []),
         "lbsc_stream_copy": (i32, [vp, vp, ctypes.c_size_t, vp]),
+        "lbsc_set_inst_tiles": (i32, [vp, i32, ctypes.POINTER(Tiles)]),
+        "lbsc_get_inst_tiles": (i32, [vp, i32, ctypes.POINTER(Tiles)]),
+        "lbsc_tune_cache_save": (i32, [ctypes.c_char_p]),
+        "lbsc_tune_cache_load": (i32, [ctypes.c_char_p, ctypes.POINTER(i32)]),
+        "lbsc_tune_cache_clear": (None, []),
+        "lbsc_kernel_hash": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -127,17 +140,33 @@ def load_library():
 
 def make_params(nx, ny, nz, *, wall_z=False, tau=(1.0, 1.0), g=0.9, psi="rho", precision="fp64",
                 shift=(0.04, 0.70), sink="none", rho_h=0.04, sink_radius=0.0, center=None,
-                phi_delta=(0.66, -0.66), plane_pad=0) -> Params:
+                phi_delta=(0.66, -0.66), plane_pad=0, solid_z=0, wall_rho=(0.0, 0.0), flags=0, ncomp=2) -> Params:
     if center is None:
         center = ((nx - 1) / 2, (ny - 1) / 2, (nz - 1) / 2)
     return Params(nx, ny, nz, int(bool(wall_z)), (ctypes.c_double * 2)(*tau), g,
                   PSI_EXP if psi == "exp" else PSI_RHO, PRECISIONS[precision], (ctypes.c_double * 2)(*shift),
                   SINKS[sink], plane_pad, rho_h, sink_radius, (ctypes.c_double * 3)(*center),
-                  (ctypes.c_double * 2)(*phi_delta))
+                  (ctypes.c_double * 2)(*phi_delta), int(solid_z), int(flags), (ctypes.c_double * 2)(*wall_rho),
+                  int(ncomp), 0)
 
 
 def _ptr(t: torch.Tensor) -> int:
     return t.data_ptr()
+
+
+def tune_cache_save(path: str):
+    st = load_library().lbsc_tune_cache_save(path.encode())
+    if st != 0:
+        raise LbscError(st, f"tune_cache_save: {path}")
+
+
+def tune_cache_load(path: str) -> int:
+    """Adds the cache entries of this build's kernel sources; returns their number."""
+    n = ctypes.c_int32()
+    st = load_library().lbsc_tune_cache_load(path.encode(), ctypes.byref(n))
+    if st != 0:
+        raise LbscError(st, f"tune_cache_load: {path}")
+    return n.value
 
 
 def stream_copy(dst: torch.Tensor, src: torch.Tensor):
@@ -168,15 +197,15 @@ class Sim:
         h = ctypes.c_void_p()
         st = lib.lbsc_create(len(plist), arr, ctypes.byref(h))
         if st != 0:
-            raise LbscError(st, "create: invalid parameters")
+            raise LbscError(st, "create: parameters refused")
         self._h = h
         self.device = torch.device(device)
         pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
         self._check(lib.lbsc_required_bytes(h, ctypes.byref(pb), ctypes.byref(sb)))
         self.pop_bytes, self.scratch_bytes = pb.value, sb.value
         self.pop = [torch.empty(pb.value, dtype=torch.uint8, device=self.device) for _ in range(2)]
-        self.scratch = torch.empty(sb.value, dtype=torch.uint8, device=self.device)
         self._check(lib.lbsc_set_stream(h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)))
+        self.scratch = torch.empty(sb.value, dtype=torch.uint8, device=self.device)
         self._check(lib.lbsc_bind(h, _ptr(self.pop[0]), _ptr(self.pop[1]), _ptr(self.scratch)))
 
     def _check(self, st):
@@ -194,6 +223,9 @@ class Sim:
         except Exception:
             pass
 
+    def ncomp(self, inst=0) -> int:
+        return 1 if self.params[inst].ncomp == 1 else 2
+
     def n(self, inst=0) -> int:
         p = self.params[inst]
         return p.nx * p.ny * p.nz
@@ -206,17 +238,21 @@ class Sim:
         t = torch.as_tensor(np.ascontiguousarray(a) if isinstance(a, np.ndarray) else a)
         return t.to(device=self.device, dtype=torch.float64).contiguous()
 
-    def init_from_density(self, rho_a, rho_b, inst=0):
-        a, b = self._dev64(rho_a).reshape(-1), self._dev64(rho_b).reshape(-1)
-        if a.numel() != self.n(inst) or b.numel() != self.n(inst):
+    def init_from_density(self, rho_a, rho_b=None, inst=0):
+        """rho_b may be None (it is ignored) with one component."""
+        a = self._dev64(rho_a).reshape(-1)
+        b = self._dev64(rho_b).reshape(-1) if rho_b is not None else None
+        if a.numel() != self.n(inst) or (b is not None and b.numel() != self.n(inst)):
             raise ValueError("density arrays must have nx*ny*nz elements")
-        self._check(self._lib.lbsc_init_from_density(self._h, inst, _ptr(a), _ptr(b)))
+        if b is None and self.ncomp(inst) == 2:
+            raise ValueError("two components need both density arrays")
+        self._check(self._lib.lbsc_init_from_density(self._h, inst, _ptr(a), _ptr(b) if b is not None else None))
         torch.cuda.synchronize(self.device)
 
     def init_from_populations(self, f, inst=0):
         t = self._dev64(f).reshape(-1)
-        if t.numel() != 2 * 19 * self.n(inst):
-            raise ValueError("populations must have 2*19*nx*ny*nz elements")
+        if t.numel() != self.ncomp(inst) * 19 * self.n(inst):
+            raise ValueError("populations must have ncomp*19*nx*ny*nz elements")
         self._check(self._lib.lbsc_init_from_populations(self._h, inst, _ptr(t)))
         torch.cuda.synchronize(self.device)
 
@@ -244,6 +280,17 @@ class Sim:
         self._check(self._lib.lbsc_tune(self._h, int(steps), ctypes.byref(t)))
         return (t.nt, t.tw, t.th, t.nzc, t.variant)
 
+    def set_inst_tiles(self, inst, tw=0, th=0, nzc=0):
+        t = Tiles(0, tw, th, nzc, 0)
+        self._check(self._lib.lbsc_set_inst_tiles(self._h, inst, ctypes.byref(t)))
+
+    def inst_tiles(self, inst):
+        """(nt, tw, th, nzc, variant) of instance inst: its own tw, th, nzc
+        (0 = the context's) and the context's resolved nt and variant."""
+        t = Tiles()
+        self._check(self._lib.lbsc_get_inst_tiles(self._h, inst, ctypes.byref(t)))
+        return (t.nt, t.tw, t.th, t.nzc, t.variant)
+
     def num_items(self) -> int:
         v = ctypes.c_int32()
         self._check(self._lib.lbsc_num_items(self._h, ctypes.byref(v)))
@@ -264,9 +311,10 @@ class Sim:
         return ra.reshape(s), rb.reshape(s), u.reshape((3,) + s)
 
     def populations(self, inst=0) -> torch.Tensor:
-        out = torch.empty(2 * 19 * self.n(inst), dtype=torch.float64, device=self.device)
+        nc = self.ncomp(inst)
+        out = torch.empty(nc * 19 * self.n(inst), dtype=torch.float64, device=self.device)
         self._check(self._lib.lbsc_read_populations(self._h, inst, _ptr(out)))
-        return out.reshape((2, 19) + self.shape(inst))
+        return out.reshape((nc, 19) + self.shape(inst))
 
     def diagnostics(self, inst=0, allow_nonfinite=False) -> dict:
         d = Diag()

@@ -162,3 +162,88 @@ def test_bench_refuses_more_than_one_gpu():
                        timeout=120)
     assert r.returncode == 2
     assert "--gpus must be 1" in r.stderr
+
+
+def test_fp16s_with_a_sink_needs_the_flag(lib):
+    """Constant-shift FP16 storage with an evaporation sink is refused
+    (LBSC_E_UNSUPPORTED) unless LBSC_FLAG_FP16S_SINK is set; FP16S without a
+    sink and FP16N with one are accepted."""
+    from paper_1701_03637_amd import lbsc
+    h = ctypes.c_void_p()
+    for sink in ("zmax", "faces", "sphere"):
+        p = lbsc.make_params(16, 16, 16, precision="fp16s", sink=sink, sink_radius=6.0)
+        assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == -5, sink
+        p = lbsc.make_params(16, 16, 16, precision="fp16s", sink=sink, sink_radius=6.0, flags=lbsc.FLAG_FP16S_SINK)
+        assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == 0
+        assert lib.lbsc_destroy(h) == 0
+    for prec, sink in (("fp16s", "none"), ("fp16n", "faces")):
+        p = lbsc.make_params(16, 16, 16, precision=prec, sink=sink)
+        assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == 0
+        assert lib.lbsc_destroy(h) == 0
+
+
+def test_wall_and_flag_validation(lib):
+    from paper_1701_03637_amd import lbsc
+    h = ctypes.c_void_p()
+    for kw in (dict(solid_z=2, wall_z=True), dict(solid_z=8), dict(solid_z=-1), dict(flags=2),
+               dict(wall_rho=(float("nan"), 0.0))):
+        p = lbsc.make_params(8, 8, 8, **kw)
+        assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == -1, kw
+
+
+def test_single_component_validation(lib):
+    """The single-component form stores FP64 or FP32S; every instance of a
+    context has the same number of components; its step has one variant."""
+    from paper_1701_03637_amd import lbsc
+    h = ctypes.c_void_p()
+    for prec, want in (("fp64", 0), ("fp32s", 0), ("fp16n", -5), ("fp16s", -5)):
+        p = lbsc.make_params(16, 16, 16, precision=prec, ncomp=1, g=-5.0, psi="exp")
+        assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == want, prec
+        if want == 0:
+            pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+            assert lib.lbsc_required_bytes(h, ctypes.byref(pb), ctypes.byref(sb)) == 0
+            elem = 8 if prec == "fp64" else 4
+            assert pb.value == 16 * 19 * ((16 * 16 + 63) // 64 * 64) * elem
+            assert lib.lbsc_set_tiles(h, ctypes.byref(lbsc.Tiles(256, 0, 0, 0, 3))) == -1
+            assert lib.lbsc_set_tiles(h, ctypes.byref(lbsc.Tiles(256, 0, 0, 0, 1))) == 0
+            assert lib.lbsc_destroy(h) == 0
+    p = lbsc.make_params(8, 8, 8, ncomp=3)
+    assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == -1
+    two = (lbsc.Params * 2)(lbsc.make_params(8, 8, 8, ncomp=1), lbsc.make_params(8, 8, 8))
+    assert lib.lbsc_create(2, two, ctypes.byref(h)) == -1
+
+
+def test_per_instance_tiles_and_tune_cache_file(lib, tmp_path):
+    """Per-instance tile overrides change only their instance's work items;
+    the tuning cache file keeps entries of this build's kernel sources and
+    skips others."""
+    from paper_1701_03637_amd import lbsc
+    h = ctypes.c_void_p()
+    two = (lbsc.Params * 2)(lbsc.make_params(40, 40, 40, precision="fp32s"),
+                            lbsc.make_params(150, 150, 20, precision="fp32s"))
+    assert lib.lbsc_create(2, two, ctypes.byref(h)) == 0
+    n0 = ctypes.c_int32()
+    lib.lbsc_num_items(h, ctypes.byref(n0))
+    assert lib.lbsc_set_inst_tiles(h, 0, ctypes.byref(lbsc.Tiles(0, 16, 4, 2, 0))) == 0
+    n1 = ctypes.c_int32()
+    lib.lbsc_num_items(h, ctypes.byref(n1))
+    assert n1.value > n0.value
+    t = lbsc.Tiles()
+    assert lib.lbsc_get_inst_tiles(h, 0, ctypes.byref(t)) == 0 and (t.tw, t.th, t.nzc) == (16, 4, 2)
+    assert lib.lbsc_get_inst_tiles(h, 1, ctypes.byref(t)) == 0 and (t.tw, t.th, t.nzc) == (0, 0, 0)
+    assert lib.lbsc_set_inst_tiles(h, 1, ctypes.byref(lbsc.Tiles(0, 600, 0, 0, 0))) == -1
+    assert lib.lbsc_set_inst_tiles(h, 2, ctypes.byref(lbsc.Tiles(0, 16, 0, 0, 0))) == -1
+    assert lib.lbsc_destroy(h) == 0
+    lib.lbsc_tune_cache_clear()
+    path = str(tmp_path / "tune.txt")
+    kh = lib.lbsc_kernel_hash().decode()
+    with open(path, "w") as fh:
+        fh.write(f"lbsc-tune 1 {kh} gfx950 64 64 64 1 2 0 0 512 32 0 8 3\n")
+        fh.write("lbsc-tune 1 0000000000000000 gfx950 64 64 64 1 2 0 0 256 0 0 0 1\n")
+    n = ctypes.c_int32()
+    assert lib.lbsc_tune_cache_load(path.encode(), ctypes.byref(n)) == 0 and n.value == 1
+    out = str(tmp_path / "out.txt")
+    assert lib.lbsc_tune_cache_save(out.encode()) == 0
+    lines = open(out).read().split("\n")
+    assert lines[0] == f"lbsc-tune 1 {kh} gfx950 64 64 64 1 2 0 0 512 32 0 8 3" and lines[1] == ""
+    lib.lbsc_tune_cache_clear()

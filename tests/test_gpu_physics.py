@@ -158,7 +158,7 @@ def test_laplace_law(surface_tension):
     assert gamma > 0
     fit = np.polyval([2 * gamma, icpt], inv_r)
     assert np.max(np.abs(fit - dp)) < 0.05 * max(dp)   # linear in 1/R
-    assert abs(icpt) < 0.10 * max(dp)                  # through the origin
+    assert abs(icpt) < 0.05 * max(dp)                  # through the origin
 
 
 def test_droplet_shrinks_like_the_radius_odes(lb, surface_tension):
@@ -207,12 +207,32 @@ def test_droplet_shrinks_like_the_radius_odes(lb, surface_tension):
     print(f"max |R - law| plain={err_plain:.3f} laplace={err_lap:.3f} gamma={gamma:.4f} D={D:.4f}")
     assert rs[-1] < r_start - 2, "droplet must evaporate"
     assert np.all(np.diff(rs) < 0)
-    # The measured radius follows the plain law to within ~5% of R while the
+    # The measured radius follows both laws to within ~6% of R while the
     # diameter exceeds 20; with D^c of Eq. (diffu-t-1) at the mean vapour
     # composition both laws run slightly fast (the same small-gradient
     # coefficient overestimates the measured decay rate of composition waves
-    # at this asymmetric composition).
+    # at this asymmetric composition), the Laplace law, being faster, a
+    # little more so.
     assert err_plain < 1.0
+    assert err_lap < 1.0
+    # The paper's claim for small droplets, on the shape of R(t), which does
+    # not depend on D: the Laplace law's ratio of shrink rates between a small
+    # and a larger radius is the closer one to the measured ratio.
+    check_rate_shape(ts, rs, lambda R: an.droplet_rate_plain(R, RH, d0, D, rho_ma0, rho_mi0, rho_h),
+                     lambda R: an.droplet_rate_laplace(R, RH, d0, D, r_start, gamma, rho_ma0, rho_mi0, rho_h),
+                     10.0, 14.0)
+
+
+def check_rate_shape(ts, rs, plain, laplace, r_small, r_large):
+    """Ratio of the shrink rates at r_small and r_large: measured (central
+    differences of R(t)) against each law's; the Laplace law must predict the
+    faster relative shrinking of small droplets and be the closer one."""
+    rate = -np.gradient(rs, ts)
+    m = np.interp(-r_small, -rs, rate) / np.interp(-r_large, -rs, rate)
+    p, q = plain(r_small) / plain(r_large), laplace(r_small) / laplace(r_large)
+    print(f"rate({r_small})/rate({r_large}): measured {m:.4f}, plain law {p:.4f}, Laplace law {q:.4f}")
+    assert q > p
+    assert abs(m - q) <= abs(m - p)
 
 
 def interface_radius(ra, r, mid):
@@ -337,3 +357,106 @@ def test_reduced_precision_diffusion_coefficient(lb, precision, nz, every, bar):
     dp = _wave_diffusion(lb, precision, nz, every)
     print(f"{precision} nz={nz}: D = {dp:.6f}, FP64 {d64:.6f}, ratio {dp / d64:.5f}")
     assert abs(dp / d64 - 1) < bar
+
+
+def _vapour_diffusion(lb, ma, mb, nz=64, amp=1e-4, every=200):
+    """D of a composition wave at mean composition (ma, mb) of the paper's
+    fluid, FP64 on the GPU: amplitude ~ exp(-D k^2 t) (Eq. (fick2))."""
+    sim = lb.Sim(lb.make_params(4, 4, nz, g=3.6, psi="exp", precision="fp64"))
+    a, b = li.sinus(4, 4, nz, ma, mb, amp)
+    sim.init_from_density(a, b)
+    s = np.sin(2 * np.pi * np.arange(nz) / nz)
+    amps, ts = [], []
+    for k in range(9):
+        if k:
+            sim.step(every)
+        amps.append((sim.density(0).cpu().numpy()[:, 0, 0] - ma) @ s / (s @ s))
+        ts.append(every * k)
+    return -np.polyfit(ts[2:], np.log(amps[2:]), 1)[0] / (2 * np.pi / nz) ** 2
+
+
+@pytest.mark.parametrize("precision", ["fp32s", "fp16n"])
+def test_droplet_128_follows_the_radius_laws(lb, surface_tension, precision):
+    """Sec. III C at half the paper's scale: a droplet of R0 = 32 in 128^3
+    with a spherical sink at R_H = 63, rho_H = 0.02, equilibrated 8000 steps,
+    then evaporating until R < 10 (the paper fits diameters above 20), in
+    FP32S and in the FP16 form for long runs (FP16N).
+
+    D is measured from a composition wave at the mean vapour composition
+    (the small-gradient formula of Eq. (diffu-t-1) overstates it there).
+    The laws are quasi-static: they hold once the vapour between droplet and
+    sink has relaxed, a few diffusion times (R_H - R0)^2 / D after the sink
+    is switched on, so they are integrated from the measured radius two
+    diffusion times in. From there R(t) stays within one lattice unit (3 %
+    of R0) of RK4 of both Eq. (mass-dfsum-sim) and Eq. (drop-r-df4) while
+    R > 20 (measured 0.83 and 0.74). Below that the droplet shrinks faster
+    than either law (at R ~ 10 both still give ~13); over the paper's range
+    (diameter > 20) the Laplace law is the closer one, in its largest error
+    (2.99 against 3.30) and on the D-independent shape of R(t) (the ratio of
+    the shrink rates at R = 12 and R = 24). M^A + E = M^A(0) and the total
+    mass hold to the storage's bar."""
+    gamma = surface_tension[0]
+    n, R0, RH, rho_h, d0 = 128, 32.0, 63.0, 0.02, 2.5
+    p = lb.make_params(n, n, n, g=3.6, psi="exp", precision=precision, shift=(0.04, 0.70), sink="none",
+                       rho_h=rho_h, sink_radius=RH, phi_delta=(0.675, -0.675))
+    sim = lb.Sim(p)
+    sim.set_graph(100)
+    a, b = li.droplet(n, n, n, R0)
+    sim.init_from_density(a, b)
+    sim.step(8000)
+    ra, rb = sim.density(0).cpu().numpy(), sim.density(1).cpu().numpy()
+    c = n // 2
+    rho_ma0 = ra[c - 2:c + 2, c - 2:c + 2, c - 2:c + 2].mean()
+    zz, yy, xx = np.meshgrid(*(np.arange(n) - (n - 1) / 2,) * 3, indexing="ij")
+    r = np.sqrt(xx ** 2 + yy ** 2 + zz ** 2)
+    shell = (r > RH - 4) & (r < RH - 1)
+    rho_mi0, rho_t = ra[shell].mean(), (ra + rb)[shell].mean()
+    del ra, rb, zz, yy, xx, r
+    sim.set_sink("sphere", rho_h, RH)
+    d_start = sim.diagnostics()
+    ts, rs = [0.0], [d_start["r_droplet"]]
+    while rs[-1] > 9.5:
+        sim.step(1000)
+        d = sim.diagnostics()
+        ts.append(ts[-1] + 1000)
+        rs.append(d["r_droplet"])
+        assert ts[-1] <= 200000, "droplet must evaporate"
+    ts, rs = np.array(ts), np.array(rs)
+    assert np.all(np.diff(rs) < 0)
+    # mass bookkeeping over the whole run: FP32 storage within 1e-6 of the
+    # total mass, FP16 storage within 1e-3
+    m0 = d_start["mass"]
+    tot = m0[0] + m0[1]
+    drift = abs(d["mass"][0] + d["mass"][1] - tot) / tot
+    drift_ae = abs(d["mass"][0] + d["evaporated"] - m0[0]) / tot
+    print(f"{precision}: total-mass drift {drift:.2e}, M^A + E drift {drift_ae:.2e}")
+    bar = 1e-6 if precision == "fp32s" else 1e-3
+    assert drift <= bar and drift_ae <= bar
+    ram = 0.5 * (rho_mi0 + rho_h)
+    D = _vapour_diffusion(lb, ram, rho_t - ram)
+
+    def plain(R):
+        return an.droplet_rate_plain(R, RH, d0, D, rho_ma0, rho_mi0, rho_h)
+
+    def laplace(R):
+        return an.droplet_rate_laplace(R, RH, d0, D, rs[0], gamma, rho_ma0, rho_mi0, rho_h)
+
+    t1 = 2 * (RH - rs[0]) ** 2 / D
+    k1 = int(np.searchsorted(ts, t1))
+    large, paper_range = rs[k1:] > 20.0, rs[k1:] > 10.0
+    errs_large, errs = [], []
+    for law in (plain, laplace):
+        t_law, r_law = an.rk4(law, rs[k1], ts[-1] - ts[k1], 100.0)
+        lawr = np.interp(ts[k1:] - ts[k1], t_law, r_law)
+        errs_large.append(np.max(np.abs(rs[k1:] - lawr)[large]))
+        errs.append(np.max(np.abs(rs[k1:] - lawr)[paper_range]))
+        print(f"{law.__name__}: {np.round(lawr[::6], 2).tolist()}")
+    print(f"R(t) every {6 * 1000} steps from t1 = {ts[k1]:.0f}: {np.round(rs[k1::6], 2).tolist()}")
+    print(f"{precision}: {len(ts)} records, R {rs[0]:.2f} -> {rs[-1]:.2f} in {ts[-1]:.0f} steps; D = {D:.4f}; "
+          f"from t1 max |R - law| while R > 20: plain {errs_large[0]:.3f}, Laplace {errs_large[1]:.3f}; "
+          f"diameter > 20: plain {errs[0]:.3f}, Laplace {errs[1]:.3f}")
+    assert max(errs_large) < 1.0
+    assert errs[1] <= errs[0]
+    check_rate_shape(ts, rs, plain, laplace, 12.0, 24.0)
+    sim.close()
+    torch.cuda.empty_cache()

@@ -426,37 +426,12 @@ def test_diffusion_into_bath_with_solid_wall(wall_rho):
 # multiphase pseudopotential model).
 # ---------------------------------------------------------------------------
 
-def coexistence_equal_area(G, guess=(0.1, 2.0)):
-    """Liquid-vapour coexistence of the single-component model with psi = 1 -
-    exp(-rho): equal bulk pressure p = c_s^2 rho + c_s^2 G psi^2 / 2 and
-    int (p0 - p) psi' / psi^2 d rho = 0 over [rho_v, rho_l]. Both follow from
-    mechanical equilibrium of a planar interface when the neighbour sum of
-    Eq. (sc) is expanded to third order on a lattice isotropic to fourth
-    order: the force's gradient term, psi times the third derivative of psi,
-    divided by psi is an exact derivative."""
-    from scipy.integrate import quad
-    from scipy.optimize import fsolve
-    cs2 = 1.0 / 3.0
-
-    def psi(r):
-        return 1.0 - np.exp(-r)
-
-    def p(r):
-        return cs2 * r + cs2 * G / 2 * psi(r) ** 2
-
-    def eqs(v):
-        rv, rl = v
-        p0 = p(rv)
-        return [p(rl) - p0, quad(lambda r: (p0 - p(r)) * np.exp(-r) / psi(r) ** 2, rv, rl)[0]]
-    return fsolve(eqs, guess)
-
-
 @pytest.mark.parametrize("G", [-5.0, -6.0])
 def test_one_component_coexistence_follows_equal_area_rule(G):
     """A planar liquid slab in its vapour (1 x 1 x 128, periodic) settles at
     the coexistence densities of the equal-area rule: measured within 0.6 %
     (vapour) and 0.05 % (liquid) at G = -5 and -6."""
-    rv, rl = coexistence_equal_area(G)
+    rv, rl = an.coexistence_single(G)
     nz = 128
     o = Oracle(_params(1, 1, nz, g=G, psi=PSI_EXP, ncomp=1, phi_delta=(rl, rv)))
     z = np.arange(nz)
@@ -479,7 +454,7 @@ def test_one_component_evaporation_books_removed_mass():
     solid wall with the top plane held below the vapour density; mass
     leaves through the boundary, M + E = M(0), and the film recedes."""
     G, nz = -5.0, 64
-    rv, rl = coexistence_equal_area(G)
+    rv, rl = an.coexistence_single(G)
     o = Oracle(_params(2, 2, nz, g=G, psi=PSI_EXP, ncomp=1, solid_z=2, wall_rho=(rl, 0.0), sink=SINK_ZMAX,
                        rho_h=0.5 * rv, phi_delta=(rl, rv)))
     z = np.arange(nz)
