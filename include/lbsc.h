@@ -194,6 +194,22 @@ lbsc_status lbsc_required_bytes(const lbsc_ctx* ctx, size_t* pop_bytes, size_t* 
 /* Binds caller-owned device buffers (borrowed until lbsc_destroy). Clears the
  * evaporation accumulators and uploads the instance table. */
 lbsc_status lbsc_bind(lbsc_ctx* ctx, void* pop0, void* pop1, void* scratch);
+/* Bytes of the per-device static scratch array used by lbsc_bind_static. */
+#define LBSC_STATIC_SCRATCH_BYTES (32 * 1024 * 1024)
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): binds the
+ * two caller-owned population buffers like lbsc_bind, with the library's own
+ * static scratch array in place of a caller scratch buffer. Allocates no
+ * device memory. The array holds LBSC_STATIC_SCRATCH_BYTES (32 MiB) on each
+ * device the library runs on, until the process ends; a context whose
+ * lbsc_required_bytes scratch exceeds it (about 1.75 bytes per lattice node:
+ * lattices up to about 2^24 nodes fit) is refused with LBSC_E_ARG. It is
+ * bound on the current device. One context per device uses the array at a
+ * time: binding another context to it takes it over, after which calls on
+ * the previous one return LBSC_E_STATE until it is bound again. Work from
+ * two contexts on one device that overlaps in time races on the array. The
+ * evaporation accumulators are cleared at bind, as with lbsc_bind. */
+lbsc_status lbsc_bind_static(lbsc_ctx* ctx, void* pop0, void* pop1);
 /* Stream for all following work (a hipStream_t; NULL = null stream). */
 lbsc_status lbsc_set_stream(lbsc_ctx* ctx, void* hip_stream);
 

@@ -19,6 +19,11 @@
 #include "kernels.h"
 #include "kernels1.h"
 
+// Scratch for contexts bound with lbsc_bind_static: one array per device,
+// held until the process ends. In host code this name is only a stand-in for
+// the symbol; its device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[LBSC_STATIC_SCRATCH_BYTES];
+
 using lbsc::Inst;
 using lbsc::Item;
 
@@ -75,6 +80,7 @@ struct lbsc_ctx {
     int nt = 256;
     int variant = 1;              // resolved k_step variant: 1 keep, 2 re-pull, 3 pipelined
     int cus = 256;                // compute units the default schedule fills
+    int static_dev = -1;          // device whose static scratch this context uses (-1: caller's buffer)
     int ncomp = 2;                // components of every instance
     size_t pop_elems = 0;         // elements per population buffer
     size_t max_items = 0;
@@ -443,11 +449,34 @@ bool steady(const lbsc_ctx* c)
     return true;
 }
 
+// Device address of each device's static scratch array and the context that
+// owns it (binding a context to it takes it over).
+constexpr int kMaxDevices = 64;
+struct StaticScratch {
+    void* ptr = nullptr;
+    const lbsc_ctx* owner = nullptr;
+};
+StaticScratch g_static[kMaxDevices];
+
+lbsc_status scratch_owned(lbsc_ctx* c)
+{
+    if (c->static_dev >= 0 && g_static[c->static_dev].owner != c)
+        return fail(c, LBSC_E_STATE, "the static scratch of device %d was taken over by another context "
+                                     "(bind this context again)", c->static_dev);
+    return LBSC_OK;
+}
+
+void release_static(lbsc_ctx* c)
+{
+    if (c->static_dev >= 0 && g_static[c->static_dev].owner == c) g_static[c->static_dev].owner = nullptr;
+    c->static_dev = -1;
+}
+
 lbsc_status check_bound(lbsc_ctx* c)
 {
     if (!c) return LBSC_E_ARG;
     if (!c->bound) return fail(c, LBSC_E_STATE, "context has no bound buffers (call lbsc_bind)");
-    return LBSC_OK;
+    return scratch_owned(c);
 }
 
 lbsc_status check_inst(lbsc_ctx* c, int inst)
@@ -492,6 +521,7 @@ lbsc_status apply_schedule(lbsc_ctx* c, const lbsc_tiles& t)
     int nt = 256, variant = 1;
     lbsc_status s = build_items(c, t, items, inst, nt, variant);
     if (s) return s;
+    if (c->bound && (s = scratch_owned(c))) return s;
     if (c->bound) {
         s = fold_eacc(c);  // accumulators belong to the old item list
         if (s) return s;
@@ -665,6 +695,7 @@ lbsc_status lbsc_destroy(lbsc_ctx* ctx)
 {
     if (!ctx) return LBSC_E_ARG;
     drop_graphs(ctx);
+    release_static(ctx);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return LBSC_OK;
@@ -712,7 +743,33 @@ static lbsc_status bind_buffers(lbsc_ctx* c, void* pop0, void* pop1, void* work)
 lbsc_status lbsc_bind(lbsc_ctx* c, void* pop0, void* pop1, void* work)
 {
     if (!c) return LBSC_E_ARG;
+    release_static(c);
     return bind_buffers(c, pop0, pop1, work);
+}
+
+lbsc_status lbsc_bind_static(lbsc_ctx* c, void* pop0, void* pop1)
+{
+    if (!c) return LBSC_E_ARG;
+    if (c->scratch_bytes > (size_t)LBSC_STATIC_SCRATCH_BYTES)
+        return fail(c, LBSC_E_ARG, "bind_static: the context needs %zu bytes of scratch, more than the %d-byte "
+                                   "static scratch", c->scratch_bytes, (int)LBSC_STATIC_SCRATCH_BYTES);
+    int dev = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(c, LBSC_E_ARG, "bind_static: device %d out of range", dev);
+    // Once per device, with that device current: the array's device address
+    // (host code must not use the symbol itself as a device pointer).
+    if (!g_static[dev].ptr) {
+        void* ptr = nullptr;
+        HIPCHK(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(c, LBSC_E_HIP, "bind_static: no address for the static scratch");
+        g_static[dev].ptr = ptr;
+    }
+    release_static(c);
+    c->static_dev = dev;
+    g_static[dev].owner = c;
+    lbsc_status s = bind_buffers(c, pop0, pop1, g_static[dev].ptr);
+    if (s) release_static(c);
+    return s;
 }
 
 // Nodes of the caller's lattice of instance inst (solid planes included),

@@ -79,7 +79,7 @@ SYMBOLS = [
     "lbsc_init_from_populations", "lbsc_set_sink", "lbsc_step", "lbsc_set_graph", "lbsc_set_tiles", "lbsc_get_tiles",
     "lbsc_tune", "lbsc_num_items", "lbsc_read_density", "lbsc_read_observables", "lbsc_read_populations",
     "lbsc_diagnostics", "lbsc_checkpoint_bytes", "lbsc_save", "lbsc_load", "lbsc_selftest",
-    "lbsc_stream_copy", "lbsc_set_inst_tiles", "lbsc_get_inst_tiles", "lbsc_tune_cache_save",
+    "lbsc_stream_copy", "lbsc_bind_static", "lbsc_set_inst_tiles", "lbsc_get_inst_tiles", "lbsc_tune_cache_save",
     "lbsc_tune_cache_load", "lbsc_tune_cache_clear", "lbsc_kernel_hash",
 ]
 
@@ -104,6 +104,7 @@ def load_library():
         "lbsc_destroy": (i32, [vp]),
         "lbsc_required_bytes": (i32, [vp, sz, sz]),
         "lbsc_bind": (i32, [vp, vp, vp, vp]),
+        "lbsc_bind_static": (i32, [vp, vp, vp]),
         "lbsc_set_stream": (i32, [vp, vp]),
         "lbsc_init_from_density": (i32, [vp, i32, vp, vp]),
         "lbsc_init_from_populations": (i32, [vp, i32, vp]),
@@ -188,7 +189,7 @@ class Sim:
     torch uint8 tensors on ``device``; the stream is torch's current stream.
     """
 
-    def __init__(self, params, device="cuda:0"):
+    def __init__(self, params, device="cuda:0", static_scratch=False):
         lib = load_library()
         self._lib = lib
         plist = params if isinstance(params, (list, tuple)) else [params]
@@ -205,8 +206,14 @@ class Sim:
         self.pop_bytes, self.scratch_bytes = pb.value, sb.value
         self.pop = [torch.empty(pb.value, dtype=torch.uint8, device=self.device) for _ in range(2)]
         self._check(lib.lbsc_set_stream(h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)))
-        self.scratch = torch.empty(sb.value, dtype=torch.uint8, device=self.device)
-        self._check(lib.lbsc_bind(h, _ptr(self.pop[0]), _ptr(self.pop[1]), _ptr(self.scratch)))
+        if static_scratch:
+            # the library's static scratch array instead of a caller buffer
+            self.scratch = None
+            with torch.cuda.device(self.device):
+                self._check(lib.lbsc_bind_static(h, _ptr(self.pop[0]), _ptr(self.pop[1])))
+        else:
+            self.scratch = torch.empty(sb.value, dtype=torch.uint8, device=self.device)
+            self._check(lib.lbsc_bind(h, _ptr(self.pop[0]), _ptr(self.pop[1]), _ptr(self.scratch)))
 
     def _check(self, st):
         if st != 0:
