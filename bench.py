@@ -128,11 +128,9 @@ def form_single(lb, torch, w, precision, steps, warmup, diag_every, graph, tune_
     a, b = densities(w)
     if pin:
         sim.set_tiles(*pin)
-    elif tune_steps:
-        # the tuner advances the state, so initialise again afterwards
-        sim.init_from_density(a, b)
-        sim.tune(tune_steps)
     sim.init_from_density(a, b)
+    if tune_steps and not pin:
+        sim.tune(tune_steps)   # leaves the initial state as it was
     del a, b
     d0 = sim.diagnostics()
     if graph:
@@ -212,12 +210,10 @@ def form_batched(lb, torch, steps, warmup, graph, tune_steps):
               for w in ws]
     sim = lb.Sim(params)
     dens = [w.densities() for w in ws]
-    if tune_steps:
-        for k, (a, b) in enumerate(dens):
-            sim.init_from_density(a, b, inst=k)
-        sim.tune(tune_steps)
     for k, (a, b) in enumerate(dens):
         sim.init_from_density(a, b, inst=k)
+    if tune_steps:
+        sim.tune(tune_steps)
     nodes = sum(w.nodes for w in ws)
     m0 = []
     for k in range(len(ws)):
@@ -248,6 +244,10 @@ def form_batched(lb, torch, steps, warmup, graph, tune_steps):
         "alg_GBps": nodes * 304 / (step_ms / steps * 1e-3) / 1e9,
         "items_per_step": sim.num_items(),
         "tiles": list(sim.tiles()),
+        # per-instance tile width, rows and chunk length picked by the size
+        # class tuner (0: the context's), by box side
+        "inst_tiles_by_side": {str(w.nx): list(sim.inst_tiles(k))[1:4] for k, w in sorted(
+            enumerate(ws), key=lambda kw: kw[1].nx)},
         "max_mass_drift_rel": drift,
     }
     res["hbm_frac_alg"] = res["alg_GBps"] / HBM_PEAK_GBPS

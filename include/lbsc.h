@@ -253,10 +253,10 @@ lbsc_status lbsc_get_tiles(const lbsc_ctx* ctx, lbsc_tiles* out);
  * size, precision, components, and for a batch the context's nt and
  * variant), valid for this build's kernel sources (lbsc_kernel_hash): a
  * one-instance context, or a size class whose every instance is cached,
- * takes its schedule from the cache without timing. The populations advance
- * during tuning (every schedule gives the same bits) and the evaporation
- * accumulators are left undefined, so call it before lbsc_init_*. The
- * graph setting is kept. */
+ * takes its schedule from the cache without timing. The state is left as
+ * it was: the timed steps read the stored populations and write only the
+ * other population buffer, and book no evaporation, so the populations, the
+ * step count and E are those before the call. The graph setting is kept. */
 lbsc_status lbsc_tune(lbsc_ctx* ctx, int32_t steps, lbsc_tiles* chosen);
 /* Tile width, rows and chunk length of instance inst (tiles->tw, th, nzc;
  * 0 = the context's; nt and variant are the context's), replacing the

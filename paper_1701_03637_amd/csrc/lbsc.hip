@@ -1038,15 +1038,31 @@ lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
+    // The live state is left as it was: every timed step reads the stored
+    // populations and writes the other buffer without making it current, and
+    // the instance table on the device books no evaporation meanwhile.
+    const int cur0 = c->cur;
+    const int64_t step0 = c->step;
+    std::vector<int32_t> count0;
+    for (auto& I : c->inst) {
+        count0.push_back(I.count_reset);
+        I.count_reset = 0;
+    }
+    auto restore = [&]() -> lbsc_status {
+        for (size_t k = 0; k < c->inst.size(); ++k) c->inst[k].count_reset = count0[k];
+        c->cur = cur0;
+        c->step = step0;
+        return upload_table(c);
+    };
     const lbsc_tiles before = c->tiles;
     const int graph_before = c->graph_steps;
     c->graph_steps = 0;
-    // Time of `n` steps of the schedule in place after a 2-step warm-up.
+    // Time of `n` steps of the schedule in place after a 2-step warm-up
+    // (each step from the stored populations; see above).
     auto time_current = [&](int n, float& ms) -> lbsc_status {
-        lbsc_status st = lbsc_step(c, 2);
-        if (st) return st;
+        for (int i = 0; i < 2; ++i) HIPCHK(c, launch_step(c, c->stream, c->cur));
         HIPCHK(c, hipEventRecord(e0, c->stream));
-        if ((st = lbsc_step(c, n))) return st;
+        for (int i = 0; i < n; ++i) HIPCHK(c, launch_step(c, c->stream, c->cur));
         HIPCHK(c, hipEventRecord(e1, c->stream));
         HIPCHK(c, hipEventSynchronize(e1));
         HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
@@ -1140,8 +1156,10 @@ lbsc_status lbsc_tune(lbsc_ctx* c, int32_t steps, lbsc_tiles* chosen)
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (s) return s;
     c->graph_steps = graph_before;
+    const lbsc_status sr = restore();
+    if (s) return s;
+    if (sr) return sr;
     if ((s = apply_schedule(c, c->tiles))) return s;
     if (c->n_inst == 1) {
         lbsc_tiles t = c->tiles;

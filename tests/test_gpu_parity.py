@@ -398,27 +398,34 @@ def test_reduced_precision_droplet_against_oracle(lb, precision, tol):
 
 
 def test_tuner_leaves_a_schedule_with_identical_results(lb):
-    """lbsc_tune times every candidate schedule on the live state (re-timing
-    its three fastest) and keeps the best; what it keeps must be a valid
-    schedule giving the same bits as the default one, and the graph setting
-    must survive the tuning."""
+    """lbsc_tune times every candidate schedule (re-timing its three fastest)
+    and keeps the best; what it keeps must be a valid schedule giving the
+    same bits as the default one. The tuning leaves the state as it was
+    (populations, step count, E), and the graph setting survives it."""
     nx, ny, nz = 40, 36, 32
     p = lb.make_params(nx, ny, nz, psi="exp", g=2.0, sink="faces", rho_h=0.03, precision="fp32s")
-    sim = lb.Sim(p)
+    sim, ref = lb.Sim(p), lb.Sim(p)
     sim.set_graph(4)
     a, b = li.droplet(nx, ny, nz, 8.0)
-    sim.init_from_density(a, b)
+    for s in (sim, ref):
+        s.init_from_density(a, b)
+        s.step(5)
+    f0, d0 = sim.populations(), sim.diagnostics()
+    assert d0["evaporated"] != 0.0
     chosen = sim.tune(3)
     assert sim.tiles() == chosen
     assert chosen[0] in (256, 512) and chosen[4] in (1, 2, 3)
-    f = sim.populations()
-    ref = lb.Sim(p)
+    assert torch.equal(sim.populations(), f0)
+    d1 = sim.diagnostics()
+    # E is refolded when the schedule changes (its sum order may move a bit)
+    assert d1["step"] == d0["step"] and d1["mass"] == d0["mass"]
+    assert abs(d1["evaporated"] - d0["evaporated"]) <= 1e-12 * abs(d0["evaporated"])
     for s in (sim, ref):
-        s.init_from_populations(f)
         s.step(6)
     assert torch.equal(sim.populations(), ref.populations())
-    d = sim.diagnostics()
-    assert d["nonfinite"] == 0
+    e, er = sim.diagnostics()["evaporated"], ref.diagnostics()["evaporated"]
+    assert abs(e - er) <= 1e-12 * abs(er)
+    assert sim.diagnostics()["nonfinite"] == 0
 
 
 def test_nonfinite_density_is_reported(lb):
