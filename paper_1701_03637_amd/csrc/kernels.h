@@ -515,7 +515,8 @@ __device__ __forceinline__ void absorb_rest(A (&f)[kQ], A total)
 //  - Collision: the residual is f_0 + sum_{i>0} (f_i - f'_i), the pre-collision
 //    rest plus the moving populations' increments. The increments are small
 //    near equilibrium, so their FP32 differences and sum carry errors far
-//    below the rest's ulp; a TwoSum gives the exact remainder to round.
+//    below the rest's ulp; a TwoSum gives the exact remainder to round. One
+//    hash per node draws for both components (16 bits each).
 //  - Sink reset: the node's stored mass is summed exactly in FP64 (19 FP32
 //    values; their exponents span far less than FP64's extra 29 bits) and E
 //    books the exact change of its A mass.
@@ -559,23 +560,54 @@ __host__ __device__ __forceinline__ float round_sr(double x, uint32_t key)
     return (r != 0.0 && u * gap < __builtin_fabs(r)) ? g : f;
 }
 
-// a + b rounded to FP32 stochastically: the exact sum is s + r (TwoSum),
-// and s moves one ulp towards r with probability |r| / ulp, from the draw
-// hash(key, bits of s and r). The gap to the neighbour is a power of two, so
-// u * gap is exact.
-__host__ __device__ __forceinline__ float round_sr_sum(float a, float b, uint32_t key)
+// TwoSum (Knuth): s = fl(a + b) and the exact remainder r = (a + b) - s.
+__host__ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& r)
 {
-    const float s = a + b;
+    s = a + b;
     const float bb = s - a;
-    const float r = (a - (s - bb)) + (b - bb);
+    r = (a - (s - bb)) + (b - bb);
+}
+
+// s + r (|r| below half an ulp of s) rounded stochastically: s, or its FP32
+// neighbour on the side of r with probability |r| / gap, decided by the
+// uniform draw u in [0, 1). The gap is a power of two, so u * gap is exact.
+__host__ __device__ __forceinline__ float sr_pick(float s, float r, float u)
+{
     uint32_t sb = __builtin_bit_cast(uint32_t, s);
     if (s == 0.0f) sb = r > 0.0f ? 1u : 0x80000001u;
     else sb += ((r > 0.0f) == (s > 0.0f)) ? 1u : 0xffffffffu;
     const float g = __builtin_bit_cast(float, sb);
     const float gap = __builtin_fabsf(g - s);
-    const uint32_t h = fmix32(key ^ fmix32(__builtin_bit_cast(uint32_t, s) ^ (__builtin_bit_cast(uint32_t, r) << 1)));
-    const float u = (float)(h >> 8) * (1.0f / 16777216.0f);
     return (r != 0.0f && u * gap < __builtin_fabsf(r)) ? g : s;
+}
+
+__host__ __device__ __forceinline__ uint32_t rotl32(uint32_t x, int k) { return (x << k) | (x >> (32 - k)); }
+
+// a + b rounded to FP32 stochastically, from a 24-bit draw that hashes the
+// key and the bits of the TwoSum pair.
+__host__ __device__ __forceinline__ float round_sr_sum(float a, float b, uint32_t key)
+{
+    float s, r;
+    two_sum(a, b, s, r);
+    const uint32_t h = fmix32(key ^ fmix32(__builtin_bit_cast(uint32_t, s) ^ (__builtin_bit_cast(uint32_t, r) << 1)));
+    return sr_pick(s, r, (float)(h >> 8) * (1.0f / 16777216.0f));
+}
+
+// The same for a node's two components at once: one hash of the key and the
+// bits of both TwoSum pairs gives each component a 16-bit draw (the rounding
+// stays unbiased to 2^-16 of an ulp).
+__host__ __device__ __forceinline__ void round_sr_sum2(const float (&a)[2], const float (&b)[2], uint32_t key,
+                                                       float (&out)[2])
+{
+    float s[2], r[2];
+    two_sum(a[0], b[0], s[0], r[0]);
+    two_sum(a[1], b[1], s[1], r[1]);
+    const uint32_t m = (key * 0x9e3779b1u) ^ __builtin_bit_cast(uint32_t, s[0]) ^
+                       (__builtin_bit_cast(uint32_t, r[0]) << 1) ^ rotl32(__builtin_bit_cast(uint32_t, s[1]), 16) ^
+                       rotl32(__builtin_bit_cast(uint32_t, r[1]), 9);
+    const uint32_t h = fmix32(m);
+    out[0] = sr_pick(s[0], r[0], (float)(h >> 16) * (1.0f / 65536.0f));
+    out[1] = sr_pick(s[1], r[1], (float)(h & 0xffffu) * (1.0f / 65536.0f));
 }
 
 // Rest population of an FP32S node whose stored deviations must sum to m
@@ -663,6 +695,10 @@ __device__ __forceinline__ void collide_node(const Inst& I, NodeVals<A>& v, cons
     const A inv_rt = recip<A>(v.rho[0] + v.rho[1]);
     const A up[3] = {(j[0][0] + j[1][0]) * inv_rt, (j[0][1] + j[1][1]) * inv_rt, (j[0][2] + j[1][2]) * inv_rt};
     const A psi[2] = {psiA, psiB};
+    // FP32S: each component's pre-collision rest and the sum of its moving
+    // populations' increments, from which the rest takes the node's exact
+    // stored mass
+    A f0[2], dsum[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const A rho = v.rho[c];
@@ -684,11 +720,9 @@ __device__ __forceinline__ void collide_node(const Inst& I, NodeVals<A>& v, cons
         const A omega = Par<A>::omega(I, c);
         // Rest: f^eq_0 = w_0 (drho + rho (-1.5 u.u)) in deviation form.
         const A base0 = drho - (A)1.5 * rho * uu;
-        const A f0 = v.f[c][0];
+        f0[c] = v.f[c][0];
+        dsum[c] = (A)0;
         v.f[c][0] = v.f[c][0] - (v.f[c][0] - (A)wgt(0) * base0) * omega;
-        // FP32S: the moving populations' increments, to give the rest the
-        // node's exact stored mass (see absorb_rest_sr)
-        A dsum = (A)0;
         // Opposite pairs (i, i+1) share w, |e.u| and the even part of q.
 #pragma unroll
         for (int i = 1; i < kQ; i += 2) {
@@ -700,13 +734,18 @@ __device__ __forceinline__ void collide_node(const Inst& I, NodeVals<A>& v, cons
             v.f[c][i] = a - (a - fp) * omega;
             v.f[c][i + 1] = b - (b - fm) * omega;
             if constexpr (EX) {
-                dsum += a - v.f[c][i];
-                dsum += b - v.f[c][i + 1];
+                dsum[c] += a - v.f[c][i];
+                dsum[c] += b - v.f[c][i + 1];
             }
         }
         // BGK conserves each component's mass exactly (sum_i f^eq_i = rho).
-        if constexpr (EX) v.f[c][0] = round_sr_sum(f0, dsum, key * 2u + (uint32_t)c);
-        else if constexpr (!kPlain<A>) absorb_rest(v.f[c], drho);
+        if constexpr (!EX && !kPlain<A>) absorb_rest(v.f[c], drho);
+    }
+    if constexpr (EX) {
+        float r0[2];
+        round_sr_sum2(f0, dsum, key, r0);
+        v.f[0][0] = r0[0];
+        v.f[1][0] = r0[1];
     }
 }
 
@@ -823,6 +862,7 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
     const int k = xcd_item(blockIdx.x, n_items);
     if (k >= n_items) return;
     const Item it = items[k];
+    if (it.nzc == 0) return;  // padding of an XCD's run of items
     const Inst I = insts[it.inst];
     const T* __restrict__ s = src + I.base;
     T* __restrict__ d = dst + I.base;
@@ -1014,6 +1054,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<S
     const int k = xcd_item(blockIdx.x, n_items);
     if (k >= n_items) return;
     const Item it = items[k];
+    if (it.nzc == 0) return;  // padding of an XCD's run of items
     const Inst I = insts[it.inst];
     const T* __restrict__ s = src + I.base;
     T* __restrict__ d = dst + I.base;

@@ -183,6 +183,7 @@ __global__ __launch_bounds__(NT) void k_step1(const Inst* __restrict__ insts, co
     const int k = xcd_item(blockIdx.x, n_items);
     if (k >= n_items) return;
     const Item it = items[k];
+    if (it.nzc == 0) return;  // padding of an XCD's run of items
     const Inst I = insts[it.inst];
     const T* __restrict__ s = src + I.base;
     T* __restrict__ d = dst + I.base;

@@ -281,6 +281,70 @@ void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int mi
             }
 }
 
+// Relative time of a work item: the nodes it pulls per plane (halo nodes,
+// mostly served by L2, at half weight) times its planes plus the two halo
+// planes of its chunk.
+double item_cost(const Item& it, const Inst& I)
+{
+    const lbsc::PipeTile p = lbsc::pipe_tile(it.tw, it.th, I.nx, I.ny);
+    return ((double)it.tw * it.th + 0.5 * p.nring) * (it.nzc + 2);
+}
+
+// Final item list: the step kernels hand XCD j the contiguous run
+// [j per, (j + 1) per) of an n = 8 per item list, so the instances' items
+// are cut into eight consecutive runs of equal cost (not equal count: the
+// items of a batch differ in size), each padded with empty items (nzc = 0)
+// to the longest run. Instances go in order of decreasing item cost, so each
+// XCD ends on its cheapest items. Every instance's items stay one range
+// [item_begin, item_end) (padding inside it books nothing).
+void place_items(const std::vector<std::vector<Item>>& per_inst, std::vector<Inst>& inst, std::vector<Item>& items)
+{
+    std::vector<int> order(per_inst.size());
+    std::vector<double> unit(per_inst.size(), 0.0);
+    for (size_t k = 0; k < per_inst.size(); ++k) {
+        order[k] = (int)k;
+        if (!per_inst[k].empty()) unit[k] = item_cost(per_inst[k][0], inst[k]);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return unit[a] > unit[b]; });
+    std::vector<Item> seq;
+    std::vector<double> cost;
+    double total = 0.0;
+    for (int k : order)
+        for (const Item& it : per_inst[k]) {
+            seq.push_back(it);
+            cost.push_back(item_cost(it, inst[k]));
+            total += cost.back();
+        }
+    // run j ends where the running cost first reaches (j + 1) / 8 of the
+    // total (each run at least as long as the one before it may need)
+    size_t cut[9];
+    cut[0] = 0;
+    double run = 0.0;
+    size_t pos = 0;
+    for (int j = 0; j < 8; ++j) {
+        const double goal = total * (j + 1) / 8.0;
+        while (pos < seq.size() && (j == 7 || run + 0.5 * cost[pos] <= goal)) run += cost[pos++];
+        cut[j + 1] = pos;
+    }
+    size_t per = 0;
+    for (int j = 0; j < 8; ++j) per = std::max(per, cut[j + 1] - cut[j]);
+    Item pad{};
+    pad.nzc = 0;
+    items.assign(8 * per, pad);
+    std::vector<int32_t> lo(inst.size(), INT32_MAX), hi(inst.size(), -1);
+    for (int j = 0; j < 8; ++j)
+        for (size_t q = cut[j]; q < cut[j + 1]; ++q) {
+            const int32_t at = (int32_t)(j * per + (q - cut[j]));
+            items[at] = seq[q];
+            lo[seq[q].inst] = std::min(lo[seq[q].inst], at);
+            hi[seq[q].inst] = std::max(hi[seq[q].inst], at);
+        }
+    for (size_t k = 0; k < inst.size(); ++k) {
+        inst[k].item_begin = hi[k] < 0 ? 0 : lo[k];
+        inst[k].item_end = hi[k] < 0 ? 0 : hi[k] + 1;
+    }
+}
+
 lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& items, std::vector<Inst>& inst, int& nt,
                         int& variant)
 {
@@ -306,7 +370,7 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
     const int min_rows = want == 3 ? 3 : 8;
     int64_t total = 0;
     for (auto& I : inst) total += I.n;
-    items.clear();
+    std::vector<std::vector<Item>> per_inst(inst.size());
     for (int k = 0; k < (int)inst.size(); ++k) {
         // an instance's own tile width, rows and chunk length override the
         // context's
@@ -316,16 +380,16 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
         if (o.th > 0) tk.th = o.th;
         if (o.nzc > 0) tk.nzc = o.nzc;
         if (tk.tw > 512 || tk.th > 512) return fail(c, LBSC_E_ARG, "instance %d: tw and th must be <= 512", k);
-        inst[k].item_begin = (int32_t)items.size();
-        instance_items(inst[k], k, tk, nt, min_rows, total, target_items, c->cus, items);
-        inst[k].item_end = (int32_t)items.size();
+        instance_items(inst[k], k, tk, nt, min_rows, total, target_items, c->cus, per_inst[k]);
     }
+    place_items(per_inst, inst, items);
     if (items.size() > c->max_items)
         return fail(c, LBSC_E_ARG, "schedule needs %zu work items, more than the %zu reserved", items.size(),
                     c->max_items);
     const int foot = nt == 256 ? lbsc::Foot<256>::kMax : lbsc::Foot<512>::kMax;
     bool pipe_fits = pipe_ok;
     for (auto& it : items) {
+        if (it.nzc == 0) continue;  // XCD padding
         if (it.tw * it.th > nt || (it.tw + 2) * (it.th + 2) > foot)
             return fail(c, LBSC_E_ARG, "internal: tile %dx%d does not fit %d threads", it.tw, it.th, nt);
         const Inst& I = inst[it.inst];
@@ -968,7 +1032,9 @@ lbsc_status lbsc_get_tiles(const lbsc_ctx* c, lbsc_tiles* out)
 lbsc_status lbsc_num_items(const lbsc_ctx* c, int32_t* n)
 {
     if (!c || !n) return LBSC_E_ARG;
-    *n = (int32_t)c->items.size();
+    int32_t real = 0;
+    for (const Item& it : c->items) real += it.nzc > 0;
+    *n = real;
     return LBSC_OK;
 }
 
@@ -1638,6 +1704,76 @@ int32_t lbsc_selftest(void)
             }
             const double gap2 = (double)hi2 - (double)lo2;
             if (std::fabs(sum2 / n - xe) > 5.0 * 0.5 * gap2 / std::sqrt((double)n) + 1e-300) ++bad;
+            // both components of a node at once (one hash, 16-bit draws:
+            // unbiased to 2^-16 of the gap beyond the sampling error)
+            const float a1 = (float)(0.3 * rnd() - 0.1), b1 = (float)((rnd() - 0.5) * 1e-3 * mag);
+            const double x1 = (double)a1 + (double)b1;
+            const float f1 = (float)x1;
+            const float lo3 = f1 <= x1 ? f1 : std::nextafter(f1, -INFINITY);
+            const float hi3 = f1 >= x1 ? f1 : std::nextafter(f1, INFINITY);
+            double s0 = 0.0, s1 = 0.0;
+            for (int k = 0; k < n; ++k) {
+                float out[2];
+                round_sr_sum2({a, a1}, {b, b1}, (uint32_t)k * 2654435761u + (uint32_t)trial, out);
+                if ((out[0] != lo2 && out[0] != hi2) || (out[1] != lo3 && out[1] != hi3)) ++bad;
+                s0 += (double)out[0];
+                s1 += (double)out[1];
+            }
+            const double gap3 = (double)hi3 - (double)lo3;
+            if (std::fabs(s0 / n - xe) > gap2 * (2.5 / std::sqrt((double)n) + 1.0 / 65536.0) + 1e-300) ++bad;
+            if (std::fabs(s1 / n - x1) > gap3 * (2.5 / std::sqrt((double)n) + 1.0 / 65536.0) + 1e-300) ++bad;
+        }
+    }
+    // Item placement: every item once, each instance's items inside its own
+    // range (with padding only), the eight XCD runs of near-equal cost, and
+    // a single instance of equal items split into equal runs without padding.
+    {
+        const int boxes[][3] = {{48, 48, 48}, {156, 156, 156}, {97, 97, 97}, {60, 60, 60}, {130, 130, 130},
+                                {49, 50, 51}, {150, 150, 20}};
+        const int single[][3] = {{128, 128, 128}, {48, 48, 48}};
+        for (int nb : {0, 1, 3, 7}) {
+            // nb = 0: one 128^3 instance (equal items)
+            const int(*bx)[3] = nb == 0 ? single : boxes;
+            nb = std::max(nb, 1);
+            std::vector<Inst> insts(nb);
+            std::vector<std::vector<Item>> per(nb);
+            int64_t total = 0, count = 0;
+            for (int k = 0; k < nb; ++k) {
+                insts[k].nx = bx[k][0]; insts[k].ny = bx[k][1]; insts[k].nz = bx[k][2];
+                insts[k].n = (int64_t)bx[k][0] * bx[k][1] * bx[k][2];
+                total += insts[k].n;
+            }
+            for (int k = 0; k < nb; ++k) {
+                instance_items(insts[k], k, lbsc_tiles{512, 0, 0, k == 1 ? 8 : 0, 0}, 512, 3, total, 4096, 256,
+                               per[k]);
+                count += (int64_t)per[k].size();
+            }
+            std::vector<Item> items;
+            place_items(per, insts, items);
+            if (items.size() % 8) ++bad;
+            const size_t run = items.size() / 8;
+            int64_t real = 0;
+            double c8[8] = {0}, cmax = 0.0;
+            for (size_t q = 0; q < items.size(); ++q) {
+                const Item& it = items[q];
+                if (it.nzc == 0) continue;
+                ++real;
+                if ((int32_t)q < insts[it.inst].item_begin || (int32_t)q >= insts[it.inst].item_end) ++bad;
+                const double cq = item_cost(it, insts[it.inst]);
+                c8[q / run] += cq;
+                cmax = std::max(cmax, cq);
+            }
+            if (real != count) ++bad;
+            for (int k = 0; k < nb; ++k)
+                for (int k2 = 0; k2 < nb; ++k2)
+                    if (k != k2 && insts[k].item_begin < insts[k2].item_end && insts[k2].item_begin < insts[k].item_end)
+                        ++bad;
+            const double mean = (c8[0] + c8[1] + c8[2] + c8[3] + c8[4] + c8[5] + c8[6] + c8[7]) / 8.0;
+            for (double cj : c8)
+                if (std::fabs(cj - mean) > cmax) ++bad;
+            bool equal = true;
+            for (const Item& it : per[0]) equal = equal && item_cost(it, insts[0]) == item_cost(per[0][0], insts[0]);
+            if (nb == 1 && equal && per[0].size() % 8 == 0 && items.size() != per[0].size()) ++bad;
         }
     }
     // Work items tile every lattice exactly once.
