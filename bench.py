@@ -368,7 +368,10 @@ def main():
     ap.add_argument("--forms", default="droplet128,large_fp64,large_fp16n,batched,film",
                     help="extra forms besides the headline (comma list, or 'none')")
     ap.add_argument("--form-steps", type=int, default=400, help="timed steps of each 2M-node form")
-    ap.add_argument("--acc-steps", type=int, default=1000, help="steps of the accuracy comparison on 128^3")
+    ap.add_argument("--acc-steps", type=int, default=1000,
+                    help="steps of the accuracy comparison on 128^3 (0: skipped, profiling aid)")
+    ap.add_argument("--d128-precisions", default="fp32s,fp64,fp16n,fp16s",
+                    help="storage forms of the 128^3 droplet form (profiling aid: a subset)")
     ap.add_argument("--graph", type=int, default=0, help="steps per HIP graph of the single-lattice forms "
                                                          "(0: direct launches)")
     ap.add_argument("--batch-graph", type=int, default=10, help="steps per HIP graph of the batch (0: direct)")
@@ -427,16 +430,18 @@ def main():
     if "droplet128" in forms:
         w2 = li.droplet_128()
         d128 = {}
-        for prec in ("fp32s", "fp64", "fp16n", "fp16s"):
+        for prec in args.d128_precisions.split(","):
             r, s = form_single(lb, torch, w2, prec, args.form_steps, 20, args.diag_every, args.graph,
                                args.tune_steps)
             s.close()
             d128[prec] = r
             print(f"# {w2.name} {prec} {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
-        acc = accuracy_runs(lb, torch, w2, ["fp32s", "fp16n", "fp16s"], args.acc_steps)
-        d128["accuracy"] = acc
-        for prec in ("fp32s", "fp16n", "fp16s"):
-            speedup_at_matched_accuracy(d128[prec], d128["fp64"], acc)
+        if args.acc_steps > 0:
+            reduced = [p for p in ("fp32s", "fp16n", "fp16s") if p in d128]
+            acc = accuracy_runs(lb, torch, w2, reduced, args.acc_steps)
+            d128["accuracy"] = acc
+            for prec in reduced:
+                speedup_at_matched_accuracy(d128[prec], d128.get("fp64"), acc)
         extra["droplet128"] = d128
         torch.cuda.empty_cache()
     if "batched" in forms:
