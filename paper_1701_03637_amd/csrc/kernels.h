@@ -453,13 +453,15 @@ __device__ __forceinline__ void store_node(typename S::T* __restrict__ dst, cons
         float hsum[2] = {0.f, 0.f};
 #pragma unroll
         for (int i = 1; i < kQ; ++i) {
-            T h[2];
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                h[c] = narrow<T>(v.f[c][i] - kRatio(i) * v.f[c][0]);
-                hsum[c] += (float)h[c];
-            }
-            bstore2(h[0], h[1], dz, xy * pair_bytes<S>(i), pair_off<S>(i, ps));
+            // each value rounds to FP32, then to FP16 (one packed conversion
+            // of the pair); the running sums read the FP16 halves directly
+            float a0 = v.f[0][i] - kRatio(i) * v.f[0][0], a1 = v.f[1][i] - kRatio(i) * v.f[1][0];
+            asm("" : "+v"(a0), "+v"(a1));
+            const H2 h = __builtin_convertvector(F2{a0, a1}, H2);
+            hsum[0] = __builtin_fmaf((float)h[0], 1.0f, hsum[0]);
+            hsum[1] = __builtin_fmaf((float)h[1], 1.0f, hsum[1]);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, h), dz, (int)(xy * pair_bytes<S>(i)),
+                                                  (int)pair_off<S>(i, ps), kStorePolicy);
         }
         bstore2(div_k(v.drho[0] - hsum[0]), div_k(v.drho[1] - hsum[1]), dz, xy * pair_bytes<S>(0),
                 pair_off<S>(0, ps));
@@ -674,7 +676,10 @@ template <typename A> __device__ __forceinline__ A recip(A x);
 template <> __device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
 template <> __device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
-template <typename A, bool EX = false>
+// RESID: the FP32 rest takes the residual drho - sum of the moving values, so
+// the node's FP32 values sum to drho; FP16N skips it, its store encodes the
+// rest from drho itself.
+template <typename A, bool EX = false, bool RESID = true>
 __device__ __forceinline__ void collide_node(const Inst& I, NodeVals<A>& v, const A S[2][3], A psiA, A psiB,
                                              uint32_t key)
 {
@@ -739,7 +744,7 @@ __device__ __forceinline__ void collide_node(const Inst& I, NodeVals<A>& v, cons
             }
         }
         // BGK conserves each component's mass exactly (sum_i f^eq_i = rho).
-        if constexpr (!EX && !kPlain<A>) absorb_rest(v.f[c], drho);
+        if constexpr (!EX && RESID && !kPlain<A>) absorb_rest(v.f[c], drho);
     }
     if constexpr (EX) {
         float r0[2];
@@ -932,7 +937,7 @@ __global__ __launch_bounds__(NT) void k_step(const Inst* __restrict__ insts, con
             force_sum<A>(psiS[sm], psiS[s0], psiS[sp], cI, rI, row, S);
             const int fc = (ty + 1) * row + tx + 1;
             const Psi2<A> pc = psiS[s0].get(fc);
-            collide_node<A, kExact<St>>(I, v, S, pc[0], pc[1], node_key(I, x, y, z));
+            collide_node<A, kExact<St>, !St::kNode>(I, v, S, pc[0], pc[1], node_key(I, x, y, z));
         }
         store_node<St>(d, I, z, xy, v);
     };
@@ -1196,7 +1201,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<S
             A S[2][3];
             force_sum<A>(psiS[dz > 0 ? sb : sa], psiS[sc0], psiS[dz > 0 ? sa : sb], sc, sr, row, S);
             const Psi2<A> pc = psiS[sc0].get(fo);
-            collide_node<A, kExact<St>>(I, v, S, pc[0], pc[1], xy + (uint32_t)z * (uint32_t)I.nx * (uint32_t)I.ny);
+            collide_node<A, kExact<St>, !St::kNode>(I, v, S, pc[0], pc[1],
+                                                    xy + (uint32_t)z * (uint32_t)I.nx * (uint32_t)I.ny);
         }
         store_node<St>(d, I, z, xy, v);
     };
