@@ -378,6 +378,9 @@ def main():
     ap.add_argument("--tiles", default="",
                     help="pin the headline schedule as nt,tw,th,nzc,variant (skips its tuner)")
     ap.add_argument("--tune-steps", type=int, default=5, help="steps per candidate of the tile tuner (0: defaults)")
+    ap.add_argument("--tune-headline", action="store_true",
+                    help="tune the headline's schedule too (by default it runs the library's default schedule, "
+                         "the one its committed profile was taken on; the tuner's picks at 512^3 are within 1 %%)")
     ap.add_argument("--cpu-steps", type=int, default=15)
     ap.add_argument("--cpu-steps-one", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -404,7 +407,7 @@ def main():
     head = None
     if not args.no_headline:
         head, sim = form_single(lb, torch, w, "fp32s", args.steps, args.warmup, args.diag_every, args.graph,
-                                args.tune_steps, pin)
+                                args.tune_steps if args.tune_headline else 0, pin)
         sim.close()
         torch.cuda.empty_cache()
         print(f"# headline {w.name} fp32s {head['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
