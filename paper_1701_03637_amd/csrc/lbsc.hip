@@ -297,7 +297,8 @@ double item_cost(const Item& it, const Inst& I)
 // to the longest run. Instances go in order of decreasing item cost, so each
 // XCD ends on its cheapest items. Every instance's items stay one range
 // [item_begin, item_end) (padding inside it books nothing).
-void place_items(const std::vector<std::vector<Item>>& per_inst, std::vector<Inst>& inst, std::vector<Item>& items)
+void place_items(const std::vector<std::vector<Item>>& per_inst, std::vector<Inst>& inst, std::vector<Item>& items,
+                 size_t max_items = SIZE_MAX)
 {
     std::vector<int> order(per_inst.size());
     std::vector<double> unit(per_inst.size(), 0.0);
@@ -328,6 +329,12 @@ void place_items(const std::vector<std::vector<Item>>& per_inst, std::vector<Ins
     }
     size_t per = 0;
     for (int j = 0; j < 8; ++j) per = std::max(per, cut[j + 1] - cut[j]);
+    if (8 * per > max_items) {
+        // padding would overflow the reserved item table (runs of very
+        // unequal counts): equal counts instead, the last run short
+        per = (seq.size() + 7) / 8;
+        for (int j = 0; j <= 8; ++j) cut[j] = std::min(seq.size(), j * per);
+    }
     Item pad{};
     pad.nzc = 0;
     items.assign(8 * per, pad);
@@ -382,7 +389,7 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
         if (tk.tw > 512 || tk.th > 512) return fail(c, LBSC_E_ARG, "instance %d: tw and th must be <= 512", k);
         instance_items(inst[k], k, tk, nt, min_rows, total, target_items, c->cus, per_inst[k]);
     }
-    place_items(per_inst, inst, items);
+    place_items(per_inst, inst, items, c->max_items);
     if (items.size() > c->max_items)
         return fail(c, LBSC_E_ARG, "schedule needs %zu work items, more than the %zu reserved", items.size(),
                     c->max_items);
@@ -1771,6 +1778,19 @@ int32_t lbsc_selftest(void)
             const double mean = (c8[0] + c8[1] + c8[2] + c8[3] + c8[4] + c8[5] + c8[6] + c8[7]) / 8.0;
             for (double cj : c8)
                 if (std::fabs(cj - mean) > cmax) ++bad;
+            // a table too small for the padding: equal counts instead
+            std::vector<Item> tight;
+            place_items(per, insts, tight, (size_t)count + 7);
+            if (tight.size() > (size_t)count + 7) ++bad;
+            int64_t real2 = 0;
+            for (size_t q = 0; q < tight.size(); ++q)
+                if (tight[q].nzc > 0) {
+                    ++real2;
+                    if ((int32_t)q < insts[tight[q].inst].item_begin || (int32_t)q >= insts[tight[q].inst].item_end)
+                        ++bad;
+                }
+            if (real2 != count) ++bad;
+            place_items(per, insts, items);   // restore the balanced ranges
             bool equal = true;
             for (const Item& it : per[0]) equal = equal && item_cost(it, insts[0]) == item_cost(per[0][0], insts[0]);
             if (nb == 1 && equal && per[0].size() % 8 == 0 && items.size() != per[0].size()) ++bad;
