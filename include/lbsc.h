@@ -249,9 +249,10 @@ lbsc_status lbsc_get_tiles(const lbsc_ctx* ctx, lbsc_tiles* out);
  * (boxes whose larger side is < 64, < 96, < 128, < 192, or more): each
  * class's tile width and chunk length (lbsc_set_inst_tiles) that make the
  * whole context's step fastest, one class after the other.
- * Results go to a process-wide cache keyed by (GPU architecture, lattice
- * size, precision, components, and for a batch the context's nt and
- * variant), valid for this build's kernel sources (lbsc_kernel_hash): a
+ * Results go to a process-wide cache keyed by (GPU architecture, fluid
+ * lattice size (nz without solid planes), precision, components, and for a
+ * batch the context's nt and variant), valid for this build's kernel
+ * sources (lbsc_kernel_hash): a
  * one-instance context, or a size class whose every instance is cached,
  * takes its schedule from the cache without timing. The state is left as
  * it was: the timed steps read the stored populations and write only the

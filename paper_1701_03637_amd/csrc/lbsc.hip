@@ -635,8 +635,9 @@ std::string device_arch()
 
 TuneKey tune_key(const lbsc_ctx* c, int inst, int nt, int variant, const std::string& arch)
 {
-    const lbsc_params& p = c->params[inst];
-    return TuneKey{arch, p.nx, p.ny, p.nz, c->precision, c->ncomp, nt, variant};
+    // the kernels' lattice: without the solid planes of a walled instance
+    const Inst& I = c->inst[inst];
+    return TuneKey{arch, I.nx, I.ny, I.nz, c->precision, c->ncomp, nt, variant};
 }
 
 bool cache_get(const TuneKey& k, lbsc_tiles& out)
