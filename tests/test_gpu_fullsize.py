@@ -132,12 +132,13 @@ def _window_reference(a, b, center, half, steps, g):
     return o.populations()[:, :, half, half, half]
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32s", 2e-6), ("fp16n", 1e-4)])
+@pytest.mark.parametrize("precision,tol", [("fp32s", 2e-6), ("fp16n", 1e-4), ("fp64", 1e-12)])
 def test_droplet512_sampled_and_properties(lb, precision, tol):
-    """The 512^3 droplet in FP32S and in its FP16 variant (FP16N). Sampled
-    populations against oracle windows: FP32S within 2e-6 (absolute; one
-    rounding of deviations below 0.25 per step), FP16N within 1e-4 (FP16
-    rounds the moving deviations, below 0.05, to 2^-11 of themselves)."""
+    """The 512^3 droplet in FP32S, in its FP16 variant (FP16N) and in FP64.
+    Sampled populations against oracle windows: FP32S within 2e-6 (absolute;
+    one rounding of deviations below 0.25 per step), FP16N within 1e-4 (FP16
+    rounds the moving deviations, below 0.05, to 2^-11 of themselves), FP64
+    within 1e-12 (summation order)."""
     w = li.droplet_512()
     steps = 3
     sim = _sim(lb, w, precision)
@@ -163,8 +164,9 @@ def test_droplet512_sampled_and_properties(lb, precision, tol):
         assert np.max(np.abs(got - ref)) < tol, (z, y, x, np.max(np.abs(got - ref)))
     d1 = sim.diagnostics()
     tot0 = d0["mass"][0] + d0["mass"][1]
-    assert abs(d1["mass"][0] + d1["mass"][1] - tot0) / tot0 < 1e-6
-    assert abs(d1["mass"][0] + d1["evaporated"] - d0["mass"][0]) / tot0 < 1e-6
+    bar_m = 1e-13 if precision == "fp64" else 1e-6
+    assert abs(d1["mass"][0] + d1["mass"][1] - tot0) / tot0 < bar_m
+    assert abs(d1["mass"][0] + d1["evaporated"] - d0["mass"][0]) / tot0 < bar_m
     rho = sim.density(0)
     # the droplet is centred on ((N-1)/2)^3: mirror symmetry up to storage
     # rounding
@@ -173,3 +175,45 @@ def test_droplet512_sampled_and_properties(lb, precision, tol):
     del f, rho
     sim.close()
     torch.cuda.empty_cache()
+
+
+def test_full_batch64_against_oracle_and_separate_runs(lb):
+    """All 64 boxes of the batch workload (48^3..156^3, 74 M nodes) in one
+    context, FP32S, 4 steps in the bench's launch configuration: every box
+    bitwise against the same box stepped alone, and against the FP64 oracle
+    (populations within 2e-6 of max|f|, the FP32S bar; M^A + E within 1e-6 of
+    the total)."""
+    ws = li.batch64()
+    params = [lb.make_params(w.nx, w.ny, w.nz, g=w.g, psi=w.psi, precision="fp32s", sink=w.sink, rho_h=w.rho_h)
+              for w in ws]
+    batch = lb.Sim(params)
+    batch.set_graph(2)
+    for k, w in enumerate(ws):
+        a, b = w.densities()
+        batch.init_from_density(a, b, inst=k)
+    steps = 4
+    batch.step(steps)
+    worst = 0.0
+    for k, w in enumerate(ws):
+        a, b = w.densities()
+        got = batch.populations(inst=k)
+        one = lb.Sim(params[k])
+        one.init_from_density(a, b)
+        one.step(steps)
+        assert torch.equal(got, one.populations()), f"instance {k} ({w.nx}^3)"
+        one.close()
+        orc = Oracle(OracleParams(w.nx, w.ny, w.nz, g=w.g, psi=PSI_RHO, sink=SINK_FACES, rho_h=w.rho_h))
+        orc.init_from_density(a, b)
+        orc.step(steps)
+        ref = orc.populations()
+        err = float(np.max(np.abs(got.cpu().numpy() - ref))) / float(np.max(np.abs(ref)))
+        worst = max(worst, err)
+        assert err <= 2e-6, (k, w.nx, err)
+        dg, do = batch.diagnostics(inst=k), orc.diagnostics()
+        tot = do["mass"][0] + do["mass"][1]
+        assert abs(dg["mass"][0] + dg["evaporated"] - (do["mass"][0] + do["evaporated"])) <= 1e-6 * tot, k
+        del orc, got, ref
+    print(f"64 boxes: worst population error {worst:.2e} of max|f|")
+    batch.close()
+    torch.cuda.empty_cache()
+
