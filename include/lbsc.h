@@ -95,9 +95,12 @@ typedef struct lbsc_params {
     double shift[2];         /* rho0^c of shifted storage (ignored for FP64) */
     int32_t sink;            /* LBSC_SINK_* */
     int32_t plane_pad;       /* extra elements between population planes
-                                (>= 0; spreads the plane streams over HBM
-                                channels: 38 per slab for FP32S, 19 planes
-                                of (A, B) pairs for FP64 and FP16); 0 = none */
+                                (0 .. 2^20; spreads the plane streams over
+                                HBM channels: 38 per slab for FP32S, 19
+                                planes of (A, B) pairs for FP64 and FP16);
+                                0 = none; -1 = automatic: 320 where a plane's
+                                byte size is a multiple of 64 KiB and it
+                                holds at least 2^14 nodes, else none */
     double rho_h;            /* density imposed on A at sink nodes */
     double sink_radius;      /* LBSC_SINK_SPHERE only */
     double center[3];        /* sphere centre (x, y, z) in node units */

@@ -58,6 +58,21 @@ int slab_planes(int prec, int ncomp)
     return prec == LBSC_FP16N ? 40 : 2 * lbsc::kQ;
 }
 
+// Elements between population planes beyond nx*ny rounded up to 64. A
+// negative plane_pad asks for the automatic skew: planes whose byte stride
+// is a multiple of 64 KiB put the same node of every plane on the same HBM
+// channels, and on the 512^3 lattice (1 MiB planes) 320 elements more
+// (1280 B in FP32) measured 6 % faster (FP32S, FP64; FP16N unchanged);
+// lattices of fewer than 2^14 nodes per plane showed no effect.
+int64_t plane_pad_of(const lbsc_params& p)
+{
+    if (p.plane_pad >= 0) return p.plane_pad;
+    const int64_t n = (int64_t)align_up((size_t)p.nx * p.ny, 64);
+    // bytes per node of one plane (pair planes hold both components)
+    const int64_t e = ncomp_of(p) == 1 ? (p.precision == LBSC_FP64 ? 8 : 4) : (p.precision == LBSC_FP64 ? 16 : 4);
+    return (n >= 16384 && (n * e) % 65536 == 0) ? 320 : 0;
+}
+
 struct CkptHeader {
     uint64_t magic;
     int32_t n_inst, precision;
@@ -173,7 +188,8 @@ lbsc_status validate(const lbsc_params& p, int k, std::string& why)
     if (p.nx < 1 || p.ny < 1 || p.nz < 1 || p.nx > 4096 || p.ny > 4096 || p.nz > 4096) return bad("size out of 1..4096");
     if ((int64_t)p.nx * p.ny * p.nz >= (int64_t(1) << 31)) return bad("nx*ny*nz must be < 2^31");
     if (p.ncomp < 0 || p.ncomp > 2) return bad("ncomp must be 0, 1 or 2");
-    if ((int64_t)slab_planes(p.precision, ncomp_of(p)) * ((int64_t)p.nx * p.ny + 64 + p.plane_pad) *
+    if (p.plane_pad < -1 || p.plane_pad > (1 << 20)) return bad("plane_pad out of -1..2^20");
+    if ((int64_t)slab_planes(p.precision, ncomp_of(p)) * ((int64_t)p.nx * p.ny + 64 + plane_pad_of(p)) *
             (int64_t)elem_size(p.precision) >= (int64_t(1) << 32))
         return bad("one z-slab of population planes must be < 4 GiB");
     if (!(p.tau[0] > 0.5) || !(p.tau[1] > 0.5)) return bad("tau must be > 0.5");
@@ -184,7 +200,6 @@ lbsc_status validate(const lbsc_params& p, int k, std::string& why)
     if (!std::isfinite(p.rho_h) || !std::isfinite(p.sink_radius)) return bad("sink parameters not finite");
     if (p.phi_delta[0] == p.phi_delta[1]) return bad("phi_delta[0] must differ from phi_delta[1]");
     if (!std::isfinite(p.shift[0]) || !std::isfinite(p.shift[1])) return bad("shift not finite");
-    if (p.plane_pad < 0 || p.plane_pad > (1 << 20)) return bad("plane_pad out of 0..2^20");
     if (p.flags & ~LBSC_FLAG_FP16S_SINK) return bad("unknown flag bits");
     if (p.solid_z < 0 || p.solid_z >= p.nz) return bad("solid_z out of 0..nz-1");
     if (p.solid_z > 0 && p.wall_z) return bad("solid_z and wall_z exclude each other");
@@ -719,7 +734,7 @@ lbsc_status lbsc_create(int32_t n_inst, const lbsc_params* params, lbsc_ctx** ou
         I.psi_exp = p.psi == LBSC_PSI_EXP;
         I.count_reset = 0;
         I.n = (int64_t)p.nx * p.ny * I.nz;
-        I.ps = (int64_t)align_up((size_t)p.nx * p.ny, 64) + (int64_t)align_up((size_t)p.plane_pad, 64);
+        I.ps = (int64_t)align_up((size_t)p.nx * p.ny, 64) + (int64_t)align_up((size_t)plane_pad_of(p), 64);
         I.slab = slab_planes(p.precision, ncomp_of(p)) * I.ps;
         I.ncomp = ncomp_of(p);
         I.base = (int64_t)off + (int64_t)h * I.slab;

@@ -141,7 +141,7 @@ def load_library():
 
 def make_params(nx, ny, nz, *, wall_z=False, tau=(1.0, 1.0), g=0.9, psi="rho", precision="fp64",
                 shift=(0.04, 0.70), sink="none", rho_h=0.04, sink_radius=0.0, center=None,
-                phi_delta=(0.66, -0.66), plane_pad=0, solid_z=0, wall_rho=(0.0, 0.0), flags=0, ncomp=2) -> Params:
+                phi_delta=(0.66, -0.66), plane_pad=-1, solid_z=0, wall_rho=(0.0, 0.0), flags=0, ncomp=2) -> Params:
     if center is None:
         center = ((nx - 1) / 2, (ny - 1) / 2, (nz - 1) / 2)
     return Params(nx, ny, nz, int(bool(wall_z)), (ctypes.c_double * 2)(*tau), g,

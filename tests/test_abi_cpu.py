@@ -61,6 +61,9 @@ def test_create_validates_and_sizes(lib):
             else:
                 setattr(q, k, v)
         assert lib.lbsc_create(1, ctypes.byref(q), ctypes.byref(h)) == -1, bad
+    for bad in (dict(plane_pad=-2), dict(plane_pad=(1 << 20) + 1)):
+        q = lbsc.make_params(8, 8, 8, **bad)
+        assert lib.lbsc_create(1, ctypes.byref(q), ctypes.byref(h)) == -1, bad
     # mixed precisions in one context are rejected
     two = (lbsc.Params * 2)(lbsc.make_params(8, 8, 8, precision="fp32s"), lbsc.make_params(8, 8, 8))
     assert lib.lbsc_create(2, two, ctypes.byref(h)) == -1
@@ -247,3 +250,31 @@ def test_per_instance_tiles_and_tune_cache_file(lib, tmp_path):
     lines = open(out).read().split("\n")
     assert lines[0] == f"lbsc-tune 1 {kh} gfx950 64 64 64 1 2 0 0 512 32 0 8 3" and lines[1] == ""
     lib.lbsc_tune_cache_clear()
+
+
+def test_automatic_plane_skew(lib):
+    """plane_pad = -1 (the binding's default) adds 320 elements between
+    population planes whose byte stride is a multiple of 64 KiB on planes of
+    at least 2^14 nodes, and nothing otherwise; explicit pads round up to 64."""
+    from paper_1701_03637_amd import lbsc
+
+    def pop_bytes(nx, ny, nz, precision, pad=-1, ncomp=2):
+        h = ctypes.c_void_p()
+        p = lbsc.make_params(nx, ny, nz, precision=precision, plane_pad=pad, ncomp=ncomp)
+        assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == 0
+        pb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+        assert lib.lbsc_required_bytes(h, ctypes.byref(pb), ctypes.byref(sb)) == 0
+        lib.lbsc_destroy(h)
+        return pb.value
+    # FP32S: 38 planes of 4-byte elements per slab
+    assert pop_bytes(128, 128, 4, "fp32s") == 4 * 38 * (128 * 128 + 320) * 4
+    assert pop_bytes(128, 128, 4, "fp32s", pad=0) == 4 * 38 * 128 * 128 * 4
+    assert pop_bytes(128, 128, 4, "fp32s", pad=100) == 4 * 38 * (128 * 128 + 128) * 4
+    assert pop_bytes(100, 100, 4, "fp32s") == 4 * 38 * ((100 * 100 + 63) // 64 * 64) * 4   # 40 000 B planes
+    assert pop_bytes(64, 64, 4, "fp32s") == 4 * 38 * 64 * 64 * 4                             # 2^12 nodes
+    # FP64 pair planes (16 B per node), FP16N (40 half-elements per node)
+    assert pop_bytes(128, 128, 2, "fp64") == 2 * 38 * (128 * 128 + 320) * 8
+    assert pop_bytes(128, 128, 2, "fp16n") == 2 * 40 * (128 * 128 + 320) * 2
+    # one component: 19 planes (the buffer ends on a 256-element boundary)
+    assert pop_bytes(128, 128, 2, "fp32s", ncomp=1) == -(-2 * 19 * (128 * 128 + 320) // 256) * 256 * 4
+

@@ -37,10 +37,10 @@ def _flags(lb, precision):
 
 
 def _pair(lb, nx, ny, nz, *, precision="fp64", psi="rho", g=0.9, tau=(1.0, 1.0), wall_z=False, sink="none",
-          rho_h=0.04, sink_radius=0.0, shift=(0.04, 0.70), phi_delta=(0.66, -0.66)):
+          rho_h=0.04, sink_radius=0.0, shift=(0.04, 0.70), phi_delta=(0.66, -0.66), plane_pad=-1):
     p = lb.make_params(nx, ny, nz, wall_z=wall_z, tau=tau, g=g, psi=psi, precision=precision, shift=shift,
                        sink=sink, rho_h=rho_h, sink_radius=sink_radius, phi_delta=phi_delta,
-                       flags=_flags(lb, precision))
+                       flags=_flags(lb, precision), plane_pad=plane_pad)
     sim = lb.Sim(p)
     orc = Oracle(OracleParams(nx, ny, nz, wall_z=wall_z, tau=tau, g=g, psi=PSI_EXP if psi == "exp" else PSI_RHO,
                               sink=SINK_CODE[sink], rho_h=rho_h, sink_radius=sink_radius, phi_delta=phi_delta))
@@ -64,11 +64,14 @@ def _cmp_pops(sim, orc, tol_rel):
          tau=(0.8, 1.3)),
     dict(dims=(1, 1, 16), psi="exp", g=3.6, sink="zmax", wall_z=True, steps=8),
     dict(dims=(70, 3, 5), psi="rho", g=1.1, sink="faces", wall_z=False, steps=4),
+    dict(dims=(13, 7, 9), psi="exp", g=2.2, sink="faces", wall_z=True, steps=5, plane_pad=100),
+    dict(dims=(128, 128, 3), psi="rho", g=0.9, sink="faces", wall_z=False, steps=3),   # automatic skew
 ])
 def test_fp64_random_populations_match_oracle(lb, case):
     nx, ny, nz = case["dims"]
     sim, orc = _pair(lb, nx, ny, nz, psi=case["psi"], g=case["g"], sink=case["sink"], wall_z=case["wall_z"],
-                     rho_h=0.03, sink_radius=case.get("sink_radius", 0.0), tau=case.get("tau", (1.0, 1.0)))
+                     rho_h=0.03, sink_radius=case.get("sink_radius", 0.0), tau=case.get("tau", (1.0, 1.0)),
+                     plane_pad=case.get("plane_pad", -1))
     f0 = li.random_populations(nx, ny, nz, seed=7, base_a=0.3, base_b=0.4, amp=0.05)
     sim.init_from_populations(f0)
     orc.init_from_populations(f0)
