@@ -370,11 +370,12 @@ void place_items(const std::vector<std::vector<Item>>& per_inst, std::vector<Ins
 lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& items, std::vector<Inst>& inst, int& nt,
                         int& variant)
 {
-    // FP32-arithmetic forms run 512-thread blocks and many short chunks by
-    // default, FP64 (register-bound at two waves per SIMD) 256-thread blocks.
+    // FP32-arithmetic forms run 512-thread blocks by default, FP64
+    // (register-bound at two waves per SIMD) 256-thread blocks; about 1024
+    // (FP32 forms) or 256 (FP64) blocks per context.
     const bool f64 = c->precision == LBSC_FP64;
     nt = t.nt > 0 ? t.nt : (f64 ? 256 : 512);
-    const int target_items = f64 ? 256 : 4096;
+    const int target_items = f64 ? 256 : 1024;
     if (nt != 256 && nt != 512) return fail(c, LBSC_E_ARG, "tiles.nt must be 256 or 512");
     if (t.variant > 3) return fail(c, LBSC_E_ARG, "tiles.variant must be 0, 1, 2 or 3");
     if (t.variant == 3 && c->precision == LBSC_FP64 && nt != 256)
