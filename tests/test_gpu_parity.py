@@ -534,6 +534,35 @@ def test_batch_under_graph_equals_separate_eager_runs(lb, precision):
     torch.cuda.empty_cache()
 
 
+def test_batch_mixing_walls_and_sinks_equals_separate_runs(lb):
+    """One context holding a solid-walled film, a seam-walled film and a
+    droplet with a spherical sink (different sizes, g, psi and rho_H): every
+    instance bitwise against the same instance stepped alone (FP32S)."""
+    params = [
+        lb.make_params(12, 10, 40, g=3.6, psi="exp", precision="fp32s", sink="zmax", rho_h=0.03, solid_z=2,
+                       wall_rho=(0.1, 0.6)),
+        lb.make_params(8, 8, 32, g=1.3, psi="rho", precision="fp32s", sink="zmax", rho_h=0.04, wall_z=True),
+        lb.make_params(30, 28, 26, g=0.95, psi="rho", precision="fp32s", sink="sphere", rho_h=0.03,
+                       sink_radius=11.0),
+    ]
+    dens = [li.film(12, 10, 40, 20), li.film(8, 8, 32, 16), li.droplet(30, 28, 26, 7.0)]
+    batch = lb.Sim(params)
+    batch.set_graph(2)
+    for k, (a, b) in enumerate(dens):
+        batch.init_from_density(a, b, inst=k)
+    batch.step(9)
+    for k, (a, b) in enumerate(dens):
+        one = lb.Sim(params[k])
+        one.init_from_density(a, b)
+        one.step(9)
+        assert torch.equal(batch.populations(inst=k), one.populations()), k
+        db, do = batch.diagnostics(inst=k), one.diagnostics()
+        assert db["mass"] == do["mass"], k
+        assert abs(db["evaporated"] - do["evaporated"]) <= 1e-12 * max(abs(do["evaporated"]), 1e-300), k
+        one.close()
+    batch.close()
+
+
 SOLID_CASES = [
     # (lattice, solid planes, wall densities, sink, psi, g)
     ((13, 7, 12), 2, (0.0, 0.0), "zmax", "exp", 3.6),
