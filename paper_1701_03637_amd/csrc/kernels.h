@@ -6,18 +6,20 @@
 // Storage. The populations of one instance live in a z-slab-major arena: the
 // populations of one z-plane form a contiguous slab, so a pull needs only the
 // three slab bases z-1, z, z+1 plus one 32-bit in-plane offset per lane.
-// Within a slab, the FP64 and FP16 forms keep population i of both
+// Within a slab, every two-component form keeps population i of both
 // components in one plane of (A, B) pairs: the two values a pull takes from
 // the same source node are adjacent and move with one load or store
-// instruction. FP32S keeps one plane per (component, population): its
-// single-element accesses are already dword-wide, and it measured faster so.
+// instruction. For FP32S that is a b64 access instead of two dword ones, which
+// doubles the bytes each outstanding memory instruction carries (512^3 step
+// 9.02 -> 8.65 ms; the 128^3 one is 1.5 % slower).
 // The stored buffer holds post-collision populations f*(t-1); the state S(t)
 // of the method (post-stream, post-sink) is obtained by pulling,
 //   f_i(x) = f*_i(x - e_i), or f*_opp(i)(x) across a z-seam wall,
 // followed by the sink reset of the sink that was active when S(t) formed.
 // Storage forms (policies St* below):
 //   FP64    f in 19 planes of (A, B) pairs, FP64 arithmetic;
-//   FP32S   38 planes of f - w_i rho0^c (constant shift), FP32 arithmetic;
+//   FP32S   f - w_i rho0^c (constant shift) in 19 pair planes, FP32
+//           arithmetic;
 //   FP16S   the same deviations in FP16, 19 pair planes, FP32 arithmetic;
 //   FP16N   per-node shift: the rest deviation d_0 = f_0 - w_0 rho0 in FP32
 //           and the 18 moving deviations as h_i = d_i - k_i d_0 of the same
@@ -46,7 +48,7 @@ namespace lbsc {
 // A, and whether the rest population carries a per-node shift (kNode).
 // kPair: (A, B) pair planes rather than one plane per component.
 struct StF64 { using T = double; using A = double; static constexpr bool kNode = false, kPair = true; };
-struct StF32S { using T = float; using A = float; static constexpr bool kNode = false, kPair = false; };
+struct StF32S { using T = float; using A = float; static constexpr bool kNode = false, kPair = true; };
 struct StF16S { using T = _Float16; using A = float; static constexpr bool kNode = false, kPair = true; };
 struct StF16N { using T = _Float16; using A = float; static constexpr bool kNode = true, kPair = true; };
 

@@ -150,12 +150,6 @@ struct Inst {
     float psi_wf[2];
 };
 
-// Arena element of population (c, i) at in-plane index xy = y*nx + x of
-// plane z: z-slab major, so the 38 planes of one z are contiguous.
-LBSC_HD int64_t eidx(const Inst& I, int c, int i, int z, int64_t xy)
-{
-    return (int64_t)z * I.slab + (int64_t)(c * kQ + i) * I.ps + xy;
-}
 
 // One block's work: an xy tile [x0, x0+tw) x [y0, y0+th) marched over z in
 // [z0, z0+nzc), upwards, or downwards when down != 0 (pipelined step only).

@@ -69,7 +69,8 @@ int64_t plane_pad_of(const lbsc_params& p)
     if (p.plane_pad >= 0) return p.plane_pad;
     const int64_t n = (int64_t)align_up((size_t)p.nx * p.ny, 64);
     // bytes per node of one plane (pair planes hold both components)
-    const int64_t e = ncomp_of(p) == 1 ? (p.precision == LBSC_FP64 ? 8 : 4) : (p.precision == LBSC_FP64 ? 16 : 4);
+    const int64_t e = ncomp_of(p) == 1 ? (p.precision == LBSC_FP64 ? 8 : 4)
+                                       : (p.precision == LBSC_FP64 ? 16 : p.precision == LBSC_FP32S ? 8 : 4);
     return (n >= 16384 && (n * e) % 65536 == 0) ? 320 : 0;
 }
 

@@ -266,12 +266,15 @@ def test_automatic_plane_skew(lib):
         assert lib.lbsc_required_bytes(h, ctypes.byref(pb), ctypes.byref(sb)) == 0
         lib.lbsc_destroy(h)
         return pb.value
-    # FP32S: 38 planes of 4-byte elements per slab
+    # FP32S: 19 planes of (A, B) pairs of 4-byte elements per slab
     assert pop_bytes(128, 128, 4, "fp32s") == 4 * 38 * (128 * 128 + 320) * 4
     assert pop_bytes(128, 128, 4, "fp32s", pad=0) == 4 * 38 * 128 * 128 * 4
     assert pop_bytes(128, 128, 4, "fp32s", pad=100) == 4 * 38 * (128 * 128 + 128) * 4
     assert pop_bytes(100, 100, 4, "fp32s") == 4 * 38 * ((100 * 100 + 63) // 64 * 64) * 4   # 40 000 B planes
     assert pop_bytes(64, 64, 4, "fp32s") == 4 * 38 * 64 * 64 * 4                             # 2^12 nodes
+    # 192 x 128 planes: 192 KiB per FP32S pair plane (skewed), 96 KiB per FP16S one (not)
+    assert pop_bytes(192, 128, 2, "fp32s") == 2 * 38 * (192 * 128 + 320) * 4
+    assert pop_bytes(192, 128, 2, "fp16s") == 2 * 38 * 192 * 128 * 2
     # FP64 pair planes (16 B per node), FP16N (40 half-elements per node)
     assert pop_bytes(128, 128, 2, "fp64") == 2 * 38 * (128 * 128 + 320) * 8
     assert pop_bytes(128, 128, 2, "fp16n") == 2 * 40 * (128 * 128 + 320) * 2
