@@ -232,13 +232,39 @@ std::vector<int> split_range(int n, int w, int parts)
     return b;
 }
 
-void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int min_rows, int64_t total_nodes,
-                    int target_items, int cus, std::vector<Item>& out)
+// Boundaries of `parts` parts of [0, n) with every inner boundary rounded
+// to a multiple of `line`; empty where rounding merges two boundaries.
+std::vector<int> split_aligned(int n, int parts, int line)
+{
+    std::vector<int> b(1, 0);
+    for (int k = 1; k < parts; ++k) {
+        const int64_t e = ((int64_t)k * n / parts + line / 2) / line * line;
+        if (e <= b.back() || e >= n) return {};
+        b.push_back((int)e);
+    }
+    b.push_back(n);
+    return b;
+}
+
+// Weight of a halo column node against a halo row node in the choice of the
+// x split: a row streams with the tile, a column node reads a cache line of
+// its own for every population. On the 512^3 lattice 128 x 4 tiles ran
+// faster than 64 x 8, which pull half the halo row nodes and twice the
+// column nodes: a column node costs more than 16 row nodes.
+constexpr double kColumnWeight = 24.0;
+
+void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int min_rows, int line,
+                    int64_t total_nodes, int target_items, int cus, std::vector<Item>& out)
 {
     // Defaults from tile sweeps on MI355X: a tile spans the whole x extent
     // (contiguous reads, no x halo) while the block still holds min_rows rows
-    // of it, else x splits evenly into parts of at most 128 (and at most
-    // nt / min_rows); as many rows as the block holds, split evenly so that
+    // of it, else x splits into near-equal parts of at most 128 (and at most
+    // nt / min_rows) whose boundaries fall on multiples of `line` nodes (one
+    // 128-byte line of a plane row) where nx is such a multiple (tiles whose
+    // rows start inside a line ran the step up to 45 % slower), of the
+    // fewest such parts and up to three more the
+    // split with the cheapest halo; as many rows as the block holds, split
+    // evenly so that
     // no block runs a thin ragged tile; about target_items blocks per context
     // with at least 16 planes per z chunk (each chunk re-derives the
     // densities of two extra planes), shorter only where 16-plane chunks
@@ -253,7 +279,29 @@ void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int mi
     } else if (I.nx <= full) {
         xb = split_range(I.nx, 0, 1);
     } else {
-        xb = split_range(I.nx, 0, (I.nx + cap - 1) / cap);
+        const int p0 = (I.nx + cap - 1) / cap;
+        // (rows start on a line only where a row is a whole number of lines)
+        const int ln = I.nx % std::max(1, line) == 0 ? std::max(1, std::min(line, cap)) : 1;
+        double best = 1e300;
+        for (int p = p0; p <= std::min(I.nx, p0 + 3); ++p) {
+            std::vector<int> b = split_aligned(I.nx, p, ln);
+            if (b.empty()) continue;
+            int wmax = 0;
+            for (size_t k = 0; k + 1 < b.size(); ++k) wmax = std::max(wmax, b[k + 1] - b[k]);
+            if (wmax > cap) continue;
+            // halo nodes per plane: two rows of nx + 2p per row of tiles, two
+            // columns of ny per part
+            const int th = std::min(I.ny, std::max(1, nt / wmax));
+            const double rows = (double)((I.ny + th - 1) / th);
+            const double cost = 2.0 * rows * (I.nx + 2.0 * p) + kColumnWeight * 2.0 * I.ny * p;
+            if (cost < best) {
+                best = cost;
+                xb = b;
+            }
+        }
+        // none rounds to widths <= cap: parts of the widest multiple of the
+        // line that fits, the last one narrower
+        if (xb.empty()) xb = split_range(I.nx, cap / ln * ln, 0);
     }
     int twmax = 0;
     for (size_t k = 0; k + 1 < xb.size(); ++k) twmax = std::max(twmax, xb[k + 1] - xb[k]);
@@ -390,6 +438,10 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
     if (c->ncomp == 1 && t.variant > 1)
         return fail(c, LBSC_E_ARG, "the single-component step has one variant (1)");
     const bool pipe_ok = c->ncomp == 2 && (!f64 || nt == 256);
+    // nodes per 128-byte line of a plane row (FP16N: of its FP32 rest pairs)
+    const int node_bytes = c->ncomp == 1 ? (int)elem_size(c->precision)
+                                         : (c->precision == LBSC_FP16N ? 8 : 2 * (int)elem_size(c->precision));
+    const int line = 128 / node_bytes;
     const int want = t.variant > 0 ? t.variant : (pipe_ok ? 3 : 1);
     const int min_rows = want == 3 ? 3 : 8;
     int64_t total = 0;
@@ -404,7 +456,7 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
         if (o.th > 0) tk.th = o.th;
         if (o.nzc > 0) tk.nzc = o.nzc;
         if (tk.tw > 512 || tk.th > 512) return fail(c, LBSC_E_ARG, "instance %d: tw and th must be <= 512", k);
-        instance_items(inst[k], k, tk, nt, min_rows, total, target_items, c->cus, per_inst[k]);
+        instance_items(inst[k], k, tk, nt, min_rows, line, total, target_items, c->cus, per_inst[k]);
     }
     place_items(per_inst, inst, items, c->max_items);
     if (items.size() > c->max_items)
@@ -1769,8 +1821,8 @@ int32_t lbsc_selftest(void)
                 total += insts[k].n;
             }
             for (int k = 0; k < nb; ++k) {
-                instance_items(insts[k], k, lbsc_tiles{512, 0, 0, k == 1 ? 8 : 0, 0}, 512, 3, total, 4096, 256,
-                               per[k]);
+                instance_items(insts[k], k, lbsc_tiles{512, 0, 0, k == 1 ? 8 : 0, 0}, 512, 3, 16, total, 4096,
+                               256, per[k]);
                 count += (int64_t)per[k].size();
             }
             std::vector<Item> items;
@@ -1816,20 +1868,25 @@ int32_t lbsc_selftest(void)
     }
     // Work items tile every lattice exactly once.
     const int dims[][3] = {{4, 4, 128}, {128, 128, 128}, {48, 48, 48}, {156, 156, 156}, {1, 1, 64}, {200, 7, 9},
-                           {4096, 2, 3}, {3, 4096, 2}, {2, 3, 4096}, {1, 1, 4096}};
+                           {4096, 2, 3}, {3, 4096, 2}, {2, 3, 4096}, {1, 1, 4096}, {512, 5, 3}, {300, 4, 2},
+                           {257, 3, 2}, {384, 6, 2}};
     for (auto& d : dims)
         for (int nt : {256, 512})
             for (int tw : {0, 8, 16, 32, 64, 128, 200, 256})
                 for (int nzc : {0, 4, 16})
                 for (int target : {256, 4096})
-                for (int min_rows : {3, 8}) {
+                for (int min_rows : {3, 8})
+                for (int line : {1, 8, 16, 32}) {
+                    if (tw > 0 && line != 16) continue;   // an explicit width ignores the line
                     Inst I{};
                     I.nx = d[0]; I.ny = d[1]; I.nz = d[2];
                     I.n = (int64_t)d[0] * d[1] * d[2];
                     std::vector<Item> items;
-                    instance_items(I, 0, lbsc_tiles{nt, tw, 0, nzc, 0}, nt, min_rows, I.n, target, 256, items);
+                    instance_items(I, 0, lbsc_tiles{nt, tw, 0, nzc, 0}, nt, min_rows, line, I.n, target, 256, items);
                     std::vector<unsigned char> cover((size_t)I.n, 0);
+                    const bool split = tw == 0 && I.nx > std::max(1, nt / min_rows);
                     for (auto& it : items) {
+                        if (split && line <= std::min(128, nt / min_rows) && I.nx % line == 0 && it.x0 % line) ++bad;
                         if (it.tw * it.th > nt) ++bad;
                         const int foot = nt == 256 ? Foot<256>::kMax : Foot<512>::kMax;
                         if ((it.tw + 2) * (it.th + 2) > foot) ++bad;
