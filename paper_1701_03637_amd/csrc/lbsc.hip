@@ -248,29 +248,32 @@ std::vector<int> split_aligned(int n, int parts, int line)
 
 // Weight of a halo column node against a halo row node in the choice of the
 // x split: a row streams with the tile, a column node reads a cache line of
-// its own for every population. On the 512^3 lattice 128 x 4 tiles ran
-// faster than 64 x 8, which pull half the halo row nodes and twice the
-// column nodes: a column node costs more than 16 row nodes.
-constexpr double kColumnWeight = 24.0;
+// its own for every population. On the 512^3 lattice FP32S ran 128 x 4 tiles
+// faster than 64 x 8 (8.68 against 9.05 ms), which pull half the halo row
+// nodes and twice the column nodes: there a column node costs more than 16
+// row nodes. The FP16 forms, bound by instruction issue rather than memory,
+// pay mostly for the decode and densities of every halo node: FP16N ran
+// 64 x 8 faster (5.55 against 5.75 ms) in the pipelined step, a column node
+// costing fewer than 16 row nodes there.
+constexpr double kColumnWeight = 24.0, kColumnWeightF16 = 8.0;
 
-void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int min_rows, int line,
+void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int min_rows, int line, double colw,
                     int64_t total_nodes, int target_items, int cus, std::vector<Item>& out)
 {
     // Defaults from tile sweeps on MI355X: a tile spans the whole x extent
     // (contiguous reads, no x halo) while the block still holds min_rows rows
-    // of it, else x splits into near-equal parts of at most 128 (and at most
-    // nt / min_rows) whose boundaries fall on multiples of `line` nodes (one
-    // 128-byte line of a plane row) where nx is such a multiple (tiles whose
-    // rows start inside a line ran the step up to 45 % slower), of the
-    // fewest such parts and up to three more the
-    // split with the cheapest halo; as many rows as the block holds, split
-    // evenly so that
-    // no block runs a thin ragged tile; about target_items blocks per context
-    // with at least 16 planes per z chunk (each chunk re-derives the
-    // densities of two extra planes), shorter only where 16-plane chunks
-    // would leave the instance fewer blocks than its share of the CUs (a
-    // block's march is latency-bound plane by plane). Explicit tw / th / nzc
-    // give fixed sizes with a ragged last tile.
+    // of it. Otherwise x splits into near-equal parts of at most 128 (and at
+    // most nt / min_rows) nodes; where nx is a whole number of `line`-node
+    // 128-byte lines the part boundaries fall on lines (tiles whose rows start
+    // inside a line ran the step up to 45 % slower), and of p0 (the fewest
+    // parts) to 4 p0 + 3 parts the split with the cheapest halo, a column node
+    // weighing `colw` row nodes, is taken. Rows: as many as the block holds,
+    // split evenly so that no block runs a thin ragged tile. Chunks: about
+    // target_items blocks per context with at least 16 planes per z chunk
+    // (each chunk re-derives the densities of two extra planes), shorter only
+    // where 16-plane chunks would leave the instance fewer blocks than its
+    // share of the CUs (a block's march is latency-bound plane by plane).
+    // Explicit tw / th / nzc give fixed sizes with a ragged last tile.
     const int full = std::max(1, nt / min_rows);
     const int cap = std::min(128, full);
     std::vector<int> xb, yb, zb;
@@ -283,7 +286,7 @@ void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int mi
         // (rows start on a line only where a row is a whole number of lines)
         const int ln = I.nx % std::max(1, line) == 0 ? std::max(1, std::min(line, cap)) : 1;
         double best = 1e300;
-        for (int p = p0; p <= std::min(I.nx, p0 + 3); ++p) {
+        for (int p = p0; p <= std::min(I.nx, 4 * p0 + 3); ++p) {
             std::vector<int> b = split_aligned(I.nx, p, ln);
             if (b.empty()) continue;
             int wmax = 0;
@@ -293,7 +296,7 @@ void instance_items(const Inst& I, int inst, const lbsc_tiles& t, int nt, int mi
             // columns of ny per part
             const int th = std::min(I.ny, std::max(1, nt / wmax));
             const double rows = (double)((I.ny + th - 1) / th);
-            const double cost = 2.0 * rows * (I.nx + 2.0 * p) + kColumnWeight * 2.0 * I.ny * p;
+            const double cost = 2.0 * rows * (I.nx + 2.0 * p) + colw * 2.0 * I.ny * p;
             if (cost < best) {
                 best = cost;
                 xb = b;
@@ -443,6 +446,8 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
                                          : (c->precision == LBSC_FP16N ? 8 : 2 * (int)elem_size(c->precision));
     const int line = 128 / node_bytes;
     const int want = t.variant > 0 ? t.variant : (pipe_ok ? 3 : 1);
+    const double colw =
+        want == 3 && (c->precision == LBSC_FP16S || c->precision == LBSC_FP16N) ? kColumnWeightF16 : kColumnWeight;
     const int min_rows = want == 3 ? 3 : 8;
     int64_t total = 0;
     for (auto& I : inst) total += I.n;
@@ -456,7 +461,7 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
         if (o.th > 0) tk.th = o.th;
         if (o.nzc > 0) tk.nzc = o.nzc;
         if (tk.tw > 512 || tk.th > 512) return fail(c, LBSC_E_ARG, "instance %d: tw and th must be <= 512", k);
-        instance_items(inst[k], k, tk, nt, min_rows, line, total, target_items, c->cus, per_inst[k]);
+        instance_items(inst[k], k, tk, nt, min_rows, line, colw, total, target_items, c->cus, per_inst[k]);
     }
     place_items(per_inst, inst, items, c->max_items);
     if (items.size() > c->max_items)
@@ -1821,8 +1826,8 @@ int32_t lbsc_selftest(void)
                 total += insts[k].n;
             }
             for (int k = 0; k < nb; ++k) {
-                instance_items(insts[k], k, lbsc_tiles{512, 0, 0, k == 1 ? 8 : 0, 0}, 512, 3, 16, total, 4096,
-                               256, per[k]);
+                instance_items(insts[k], k, lbsc_tiles{512, 0, 0, k == 1 ? 8 : 0, 0}, 512, 3, 16, kColumnWeight,
+                               total, 4096, 256, per[k]);
                 count += (int64_t)per[k].size();
             }
             std::vector<Item> items;
@@ -1882,7 +1887,8 @@ int32_t lbsc_selftest(void)
                     I.nx = d[0]; I.ny = d[1]; I.nz = d[2];
                     I.n = (int64_t)d[0] * d[1] * d[2];
                     std::vector<Item> items;
-                    instance_items(I, 0, lbsc_tiles{nt, tw, 0, nzc, 0}, nt, min_rows, line, I.n, target, 256, items);
+                    instance_items(I, 0, lbsc_tiles{nt, tw, 0, nzc, 0}, nt, min_rows, line,
+                                   line == 32 ? kColumnWeightF16 : kColumnWeight, I.n, target, 256, items);
                     std::vector<unsigned char> cover((size_t)I.n, 0);
                     const bool split = tw == 0 && I.nx > std::max(1, nt / min_rows);
                     for (auto& it : items) {

@@ -125,7 +125,10 @@ def test_default_tiles_split_evenly(lib):
     in 9 chunks, a 300-wide box three 100-wide tiles of 5 rows. Where a row
     is a whole number of 128-byte lines, part boundaries fall on lines: a
     512-wide FP64 box gets eight 64 x 4 tiles rather than seven 73 or 74
-    wide. The 128^3 droplet gets 32 tiles of 128 x 4 in 8 chunks of 16 planes (FP64, 256
+    wide, FP32S 128 x 4 tiles, and the pipelined FP16 forms (bound by
+    instruction issue, so halo nodes cost more than halo columns) 64-wide
+    tiles.
+    The 128^3 droplet gets 32 tiles of 128 x 4 in 8 chunks of 16 planes (FP64, 256
     threads: 64 tiles of 64 x 4 in 4 chunks). Chunks shorter than 16 planes
     are made only until the blocks number the 256 CUs: 11 chunks of the
     32-plane box's 24 tiles, one-plane chunks of the 4x4x128 film."""
@@ -146,6 +149,8 @@ def test_default_tiles_split_evenly(lib):
     assert items((300, 40, 32), "fp32s") == 3 * 8 * 11                  # ceil(256 / 24) chunks
     assert items((384, 40, 32), "fp32s") == 3 * 10 * 9                  # 128 x 4 tiles; ceil(256 / 30) chunks
     assert items((512, 16, 16), "fp64") == 8 * 4 * 8                    # 64 x 4 tiles, not 7 parts of 73
+    assert items((512, 20, 16), "fp32s") == 4 * 5 * 13                  # 128 x 4 tiles
+    assert items((512, 20, 16), "fp16n") == 8 * 3 * 11                  # 64 x 7: halo columns weigh less
     assert items((128, 128, 128), "fp32s") == 32 * 8
     assert items((128, 128, 128), "fp64") == 64 * 4
     assert items((4, 4, 128), "fp64") == 128
