@@ -245,6 +245,10 @@ PIPE_CASES = [
     ((150, 7, 9), False, "faces", (512, 0, 0, 0, 3)),
     ((200, 5, 11), True, "zmax", (512, 200, 2, 0, 3)),
     ((40, 24, 21), False, "sphere", (256, 40, 6, 4, 3), (0.8, 1.3)),
+    # default splits of a 512-wide lattice on 128-byte lines: FP64 into
+    # 64-wide parts, FP32S 128-wide, the FP16 forms 64-wide
+    ((512, 20, 9), False, "faces", (256, 0, 0, 0, 3)),
+    ((512, 20, 9), False, "faces", (512, 0, 0, 0, 3)),
     # extents at the 4096 limit, default tiles and chunks
     ((4096, 2, 3), False, "none", (256, 0, 0, 0, 3)),
     ((2, 3, 4096), True, "zmax", (512, 0, 0, 0, 3)),
