@@ -254,7 +254,7 @@ lbsc_status lbsc_get_tiles(const lbsc_ctx* ctx, lbsc_tiles* out);
  * whole context's step fastest, one class after the other.
  * Results go to a process-wide cache keyed by (GPU architecture, fluid
  * lattice size (nz without solid planes), precision, components, and for a
- * batch the context's nt and variant), valid for this build's kernel
+ * batch the context's nt and variant), valid for the compiled kernel
  * sources (lbsc_kernel_hash): a
  * one-instance context, or a size class whose every instance is cached,
  * takes its schedule from the cache without timing. The state is left as

@@ -685,7 +685,7 @@ lbsc_status apply_schedule(lbsc_ctx* c, const lbsc_tiles& t)
 }
 
 // Tuning cache: schedules the tuner kept, by (architecture, lattice size,
-// precision, components, context nt, context variant), for this build's
+// precision, components, context nt, context variant), for the compiled
 // kernel sources (LBSC_KERNEL_HASH, a hash of their code). A one-instance
 // context stores its whole schedule under nt = variant = 0; an instance of a
 // batch its tile width, rows and chunk length under the batch's nt and

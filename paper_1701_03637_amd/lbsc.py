@@ -162,7 +162,7 @@ def tune_cache_save(path: str):
 
 
 def tune_cache_load(path: str) -> int:
-    """Adds the cache entries of this build's kernel sources; returns their number."""
+    """Adds the cache entries of the loaded library's kernel sources; returns their number."""
     n = ctypes.c_int32()
     st = load_library().lbsc_tune_cache_load(path.encode(), ctypes.byref(n))
     if st != 0:

@@ -227,7 +227,7 @@ def test_single_component_validation(lib):
 
 def test_per_instance_tiles_and_tune_cache_file(lib, tmp_path):
     """Per-instance tile overrides change only their instance's work items;
-    the tuning cache file keeps entries of this build's kernel sources and
+    the tuning cache file keeps entries of the loaded library's kernel sources and
     skips others."""
     from paper_1701_03637_amd import lbsc
     h = ctypes.c_void_p()
