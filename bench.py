@@ -7,7 +7,7 @@ FP64 diagnostics every --diag-every steps are inside the timed region). It is
 the largest configuration that fits one GPU.
 
 Extra forms on the same line:
-  - the 128^3 droplet in FP32S, FP64, FP16N and FP16S;
+  - the 128^3 droplet in FP32S, FP64, FP16N, FP16NF and FP16S;
   - the 512^3 droplet in FP64 and in its FP16 variant (FP16N);
   - the 64 batched uneven droplets (48^3..156^3) in one launch per step,
     replayed as HIP graphs, against 64 separate contexts;
@@ -36,12 +36,13 @@ METRIC = "2-comp D3Q19 MLUPS + % HBM peak; FP32/FP16/batched vs plain FP64 at st
 HBM_PEAK_GBPS = 8000.0
 # 2 comps x 19 x (read + write) x element size; FP16N stores the rest
 # population in FP32 (2 x 2 x (18 x 2 + 4))
-BYTES_PER_LU = {"fp64": 608, "fp32s": 304, "fp16s": 152, "fp16n": 160}
-DTYPE = {"fp64": "f64", "fp32s": "f32", "fp16s": "f32", "fp16n": "f32"}
+BYTES_PER_LU = {"fp64": 608, "fp32s": 304, "fp16s": 152, "fp16n": 160, "fp16nf": 160}
+DTYPE = {"fp64": "f64", "fp32s": "f32", "fp16s": "f32", "fp16n": "f32", "fp16nf": "f32"}
 # Accuracy bars against the FP64 run of the same workload and steps: max
 # |rho_A - rho_A(FP64)|, and the relative drifts of M^A + M^B and M^A + E.
 BARS = {"fp32s": {"max_abs_drho": 1e-5, "mass_drift": 1e-6},
         "fp16n": {"max_abs_drho": 1e-3, "mass_drift": 1e-6},
+        "fp16nf": {"max_abs_drho": 1e-3, "mass_drift": 1e-6},
         "fp16s": {"max_abs_drho": 1e-3, "mass_drift": 1e-3}}
 
 
@@ -370,7 +371,7 @@ def main():
     ap.add_argument("--form-steps", type=int, default=400, help="timed steps of each 2M-node form")
     ap.add_argument("--acc-steps", type=int, default=1000,
                     help="steps of the accuracy comparison on 128^3 (0: skipped, profiling aid)")
-    ap.add_argument("--d128-precisions", default="fp32s,fp64,fp16n,fp16s",
+    ap.add_argument("--d128-precisions", default="fp32s,fp64,fp16n,fp16nf,fp16s",
                     help="storage forms of the 128^3 droplet form (profiling aid: a subset)")
     ap.add_argument("--graph", type=int, default=0, help="steps per HIP graph of the single-lattice forms "
                                                          "(0: direct launches)")
@@ -440,7 +441,7 @@ def main():
             d128[prec] = r
             print(f"# {w2.name} {prec} {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         if args.acc_steps > 0:
-            reduced = [p for p in ("fp32s", "fp16n", "fp16s") if p in d128]
+            reduced = [p for p in ("fp32s", "fp16n", "fp16nf", "fp16s") if p in d128]
             acc = accuracy_runs(lb, torch, w2, reduced, args.acc_steps)
             d128["accuracy"] = acc
             for prec in reduced:

@@ -67,9 +67,14 @@ typedef enum lbsc_status {
  * FP16N stores a per-node shift: the rest deviation d_0 = f_0 - w_0 shift[c]
  * in FP32 and the moving deviations as d_i - (w_i/w_0) d_0 of the same node
  * in FP16 (zero at rest equilibrium; 160 bytes per lattice update), FP32
- * arithmetic.
+ * arithmetic. FP16NF stores the same with the moving deviations times 2^12:
+ * deviations down to 1.5e-8 (rather than FP16's smallest normal 6.1e-5) keep
+ * FP16's 11 significant bits, which slow diffusion through near-uniform
+ * regions needs (its diffusion coefficient matches FP64's where FP16N's comes
+ * out low); |d_i - (w_i/w_0) d_0| must stay below 16, and its step costs a
+ * few percent more than FP16N's (one more operation per decoded value).
  * Global sums (mass, evaporated mass, interface) are FP64 in every form. */
-enum { LBSC_FP64 = 0, LBSC_FP32S = 1, LBSC_FP16S = 2, LBSC_FP16N = 3 };
+enum { LBSC_FP64 = 0, LBSC_FP32S = 1, LBSC_FP16S = 2, LBSC_FP16N = 3, LBSC_FP16NF = 4 };
 enum { LBSC_PSI_RHO = 0, LBSC_PSI_EXP = 1 };
 /* Sink node sets: the plane z = nz-1; the six faces; all nodes at distance
  * >= sink_radius from center. */
@@ -91,7 +96,7 @@ typedef struct lbsc_params {
     double tau[2];           /* relaxation times tau^A, tau^B (> 0.5) */
     double g;                /* interaction strength g^{AB} = g^{BA} */
     int32_t psi;             /* LBSC_PSI_RHO or LBSC_PSI_EXP */
-    int32_t precision;       /* LBSC_FP64/FP32S/FP16S/FP16N; equal for all instances */
+    int32_t precision;       /* LBSC_FP64/FP32S/FP16S/FP16N/FP16NF; equal for all instances */
     double shift[2];         /* rho0^c of shifted storage (ignored for FP64) */
     int32_t sink;            /* LBSC_SINK_* */
     int32_t plane_pad;       /* extra elements between population planes
@@ -166,10 +171,10 @@ typedef struct lbsc_ctx lbsc_ctx;
  * kernel variant: 1 keeps a node's pulled populations in registers from its
  * density pass to its collision, 2 pulls the node again for the collision
  * (fewer registers, more blocks per CU), 3 (FP64 with nt = 256, FP32S,
- * FP16S, FP16N) also keeps them but issues each plane's loads one plane ahead
+ * FP16S, FP16N, FP16NF) also keeps them but issues each plane's loads one plane ahead
  * of use, with one barrier per plane; it needs one thread per halo node of a
  * tile (the halo of a tile spanning the whole x or y extent is the tile
- * itself), and for FP16N (tw + 4)(th + 4) <= 3 nt (the rest values of the
+ * itself), and for FP16N and FP16NF (tw + 4)(th + 4) <= 3 nt (the rest values of the
  * tile and two halo rings are staged through LDS), so tiles that break this
  * are rejected. Variants give bitwise
  * identical populations. Zero or negative fields mean "choose automatically"

@@ -46,11 +46,30 @@ namespace lbsc {
 
 // Storage policies: element type T of the population planes, arithmetic type
 // A, and whether the rest population carries a per-node shift (kNode).
-// kPair: (A, B) pair planes rather than one plane per component.
+// kPair: (A, B) pair planes rather than one plane per component. kHS (per-node
+// forms): the power of two the stored FP16 moving values are scaled by.
 struct StF64 { using T = double; using A = double; static constexpr bool kNode = false, kPair = true; };
 struct StF32S { using T = float; using A = float; static constexpr bool kNode = false, kPair = true; };
 struct StF16S { using T = _Float16; using A = float; static constexpr bool kNode = false, kPair = true; };
-struct StF16N { using T = _Float16; using A = float; static constexpr bool kNode = true, kPair = true; };
+struct StF16N {
+    using T = _Float16;
+    using A = float;
+    static constexpr bool kNode = true, kPair = true;
+    static constexpr float kHS = 1.0f;
+};
+// FP16NF: FP16N with the moving values stored as 2^12 (d_i - k_i d_0). In the
+// near-uniform regions of a slow diffusion those deviations are of order
+// 1e-7, below FP16's smallest normal number (6.1e-5), where FP16 keeps only
+// an absolute step of 6e-8 and rounds away most of the diffusive flux they
+// carry. Scaled, they keep FP16's 11 significant bits down to 1.5e-8; the
+// deviations must stay below 16 in magnitude. Scaling by a power of two is
+// exact in FP32; the decode then takes one more operation per value.
+struct StF16NF {
+    using T = _Float16;
+    using A = float;
+    static constexpr bool kNode = true, kPair = true;
+    static constexpr float kHS = 4096.0f;
+};
 
 // Slab elements (of T) per in-plane element: 2 x 19 values, or for FP16N
 // 18 planes of FP16 pairs plus one plane of FP32 rest pairs (= 4 FP16
@@ -70,6 +89,16 @@ constexpr float kInvKLo = (float)(1.0 / kK - (double)kInvK);
 
 // y / K rounded once (to within a tail rounding): head product plus tail.
 __device__ __forceinline__ float div_k(float y) { return __builtin_fmaf(y, kInvK, y * kInvKLo); }
+
+// Decode of a per-node form's moving value: d_i = k_i d_0(source) + h_i / kHS,
+// rounded once (h_i / kHS is exact). Every decode site computes exactly this.
+template <class S> __device__ __forceinline__ float decode_h(float k, float d0, _Float16 h)
+{
+    if constexpr (S::kHS == 1.0f)
+        return __builtin_fmaf(k, d0, (float)h);
+    else
+        return __builtin_fmaf(k, d0, __builtin_fmaf((float)h, 1.0f / S::kHS, 0.0f));
+}
 
 // Narrowing of an arithmetic value to the storage type. An FP32 value bound
 // for FP16 is formed in a register first: otherwise the compiler may fuse
@@ -245,7 +274,7 @@ template <typename A, int FP> struct PsiPlane<A, FP, false> {
     }
     __device__ __forceinline__ Psi2<A> get(int i) const { return Psi2<A>{v[0][i], v[1][i]}; }
 };
-template <class S> constexpr bool kPsiPair = std::is_same_v<S, StF32S> || std::is_same_v<S, StF16N>;
+template <class S> constexpr bool kPsiPair = std::is_same_v<S, StF32S> || S::kNode;
 
 template <typename T> __device__ __forceinline__ Pair<T> bload2(Rsrc r, uint32_t voff, uint32_t soff);
 template <> __device__ __forceinline__ Pair<float> bload2<float>(Rsrc r, uint32_t voff, uint32_t soff)
@@ -421,8 +450,8 @@ __device__ __forceinline__ void decode_raw(const RawNode<S>& w, NodeVals<A>& v)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             if constexpr (S::kNode) {
-                // d_i = k_i d_0(source) + h_i(source)
-                v.f[c][i] = i == 0 ? w.d0[c][0] : kRatio(i) * w.d0[c][i] + (float)w.h2[i][c];
+                // d_i = k_i d_0(source) + h_i(source) / kHS
+                v.f[c][i] = i == 0 ? w.d0[c][0] : decode_h<S>(kRatio(i), w.d0[c][i], w.h2[i][c]);
             } else if constexpr (kHalfPair<S>) {
                 v.f[c][i] = (A)w.v2[i][c];
             } else {
@@ -449,19 +478,24 @@ __device__ __forceinline__ void store_node(typename S::T* __restrict__ dst, cons
     const Rsrc dz = slab_rsrc(dst + (int64_t)z * I.slab);
     const uint32_t ps = (uint32_t)I.ps;
     if constexpr (S::kNode) {
-        // moving deviations relative to k_i d_0 in FP16; the rest deviation
-        // takes their rounding so the decoded node sums to drho (up to FP32
-        // rounding).
+        // moving deviations relative to k_i d_0 in FP16 (times kHS); the rest
+        // deviation takes their rounding so the decoded node sums to drho (up
+        // to FP32 rounding).
         float hsum[2] = {0.f, 0.f};
 #pragma unroll
         for (int i = 1; i < kQ; ++i) {
-            // each value rounds to FP32, then to FP16 (one packed conversion
-            // of the pair); the running sums read the FP16 halves directly
+            // each value rounds to FP32, is scaled exactly, then rounds to
+            // FP16 (one packed conversion of the pair); the running sums read
+            // the FP16 halves directly, unscaled exactly
             float a0 = v.f[0][i] - kRatio(i) * v.f[0][0], a1 = v.f[1][i] - kRatio(i) * v.f[1][0];
+            if constexpr (S::kHS != 1.0f) {
+                a0 *= S::kHS;
+                a1 *= S::kHS;
+            }
             asm("" : "+v"(a0), "+v"(a1));
             const H2 h = __builtin_convertvector(F2{a0, a1}, H2);
-            hsum[0] = __builtin_fmaf((float)h[0], 1.0f, hsum[0]);
-            hsum[1] = __builtin_fmaf((float)h[1], 1.0f, hsum[1]);
+            hsum[0] = __builtin_fmaf((float)h[0], 1.0f / S::kHS, hsum[0]);
+            hsum[1] = __builtin_fmaf((float)h[1], 1.0f / S::kHS, hsum[1]);
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, h), dz, (int)(xy * pair_bytes<S>(i)),
                                                   (int)pair_off<S>(i, ps), kStorePolicy);
         }
@@ -1300,7 +1334,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kPipeWaves<S
                                               : restS[(me - dz * e + 2) & 3][(int)b - ey(i) * W - ex(i)];
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
-                    v.f[c][i] = i == 0 ? d[c] : kRatio(i) * d[c] + (float)w.h2[i][c];
+                    v.f[c][i] = i == 0 ? d[c] : decode_h<St>(kRatio(i), d[c], w.h2[i][c]);
             }
         };
         RawH<St> ro, rr;
@@ -1433,7 +1467,10 @@ __device__ __forceinline__ void put_slot(typename S::T* __restrict__ d, const In
     if constexpr (S::kNode) {
         const float d0 = (float)(f0 - wgt(0) * I.shift[c]);
         if (i == 0) *reinterpret_cast<float*>(slab + off) = d0;
-        else *reinterpret_cast<T*>(slab + off) = narrow<T>((float)(val - wgt(i) * I.shift[c]) - kRatio(i) * d0);
+        else {
+            const float a = (float)(val - wgt(i) * I.shift[c]) - kRatio(i) * d0;
+            *reinterpret_cast<T*>(slab + off) = narrow<T>(a * S::kHS);
+        }
     } else {
         *reinterpret_cast<T*>(slab + off) = (T)(A)(val - wgt(i) * I.shift[c]);
     }

@@ -47,6 +47,10 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 size_t elem_size(int prec) { return prec == LBSC_FP64 ? 8 : (prec == LBSC_FP32S ? 4 : 2); }
 
+// The per-node-shift FP16 forms (FP16N, FP16NF): FP32 rest pairs, FP16 moving
+// pairs.
+bool per_node(int prec) { return prec == LBSC_FP16N || prec == LBSC_FP16NF; }
+
 // Components of an instance: 1 (single-component multiphase form) or 2.
 int ncomp_of(const lbsc_params& p) { return p.ncomp == 1 ? 1 : 2; }
 
@@ -55,7 +59,7 @@ int ncomp_of(const lbsc_params& p) { return p.ncomp == 1 ? 1 : 2; }
 int slab_planes(int prec, int ncomp)
 {
     if (ncomp == 1) return lbsc::kSlabPlanes1;
-    return prec == LBSC_FP16N ? 40 : 2 * lbsc::kQ;
+    return per_node(prec) ? 40 : 2 * lbsc::kQ;
 }
 
 // Elements between population planes beyond nx*ny rounded up to 64. A
@@ -196,7 +200,7 @@ lbsc_status validate(const lbsc_params& p, int k, std::string& why)
     if (!(p.tau[0] > 0.5) || !(p.tau[1] > 0.5)) return bad("tau must be > 0.5");
     if (!std::isfinite(p.g)) return bad("g not finite");
     if (p.psi != LBSC_PSI_RHO && p.psi != LBSC_PSI_EXP) return bad("unknown psi");
-    if (p.precision < LBSC_FP64 || p.precision > LBSC_FP16N) return bad("unknown precision");
+    if (p.precision < LBSC_FP64 || p.precision > LBSC_FP16NF) return bad("unknown precision");
     if (p.sink < LBSC_SINK_NONE || p.sink > LBSC_SINK_SPHERE) return bad("unknown sink kind");
     if (!std::isfinite(p.rho_h) || !std::isfinite(p.sink_radius)) return bad("sink parameters not finite");
     if (p.phi_delta[0] == p.phi_delta[1]) return bad("phi_delta[0] must differ from phi_delta[1]");
@@ -443,11 +447,11 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
     const bool pipe_ok = c->ncomp == 2 && (!f64 || nt == 256);
     // nodes per 128-byte line of a plane row (FP16N: of its FP32 rest pairs)
     const int node_bytes = c->ncomp == 1 ? (int)elem_size(c->precision)
-                                         : (c->precision == LBSC_FP16N ? 8 : 2 * (int)elem_size(c->precision));
+                                         : (per_node(c->precision) ? 8 : 2 * (int)elem_size(c->precision));
     const int line = 128 / node_bytes;
     const int want = t.variant > 0 ? t.variant : (pipe_ok ? 3 : 1);
     const double colw =
-        want == 3 && (c->precision == LBSC_FP16S || c->precision == LBSC_FP16N) ? kColumnWeightF16 : kColumnWeight;
+        want == 3 && (c->precision == LBSC_FP16S || per_node(c->precision)) ? kColumnWeightF16 : kColumnWeight;
     const int min_rows = want == 3 ? 3 : 8;
     int64_t total = 0;
     for (auto& I : inst) total += I.n;
@@ -478,12 +482,12 @@ lbsc_status build_items(lbsc_ctx* c, const lbsc_tiles& t, std::vector<Item>& ite
             it.z0 + it.nzc > I.nz || it.tw < 1 || it.th < 1 || it.nzc < 1)
             return fail(c, LBSC_E_ARG, "internal: tile outside its lattice");
         if (lbsc::pipe_tile(it.tw, it.th, I.nx, I.ny).nring > nt) pipe_fits = false;
-        if (c->precision == LBSC_FP16N && !lbsc::rest_fits(it.tw, it.th, nt)) pipe_fits = false;
+        if (per_node(c->precision) && !lbsc::rest_fits(it.tw, it.th, nt)) pipe_fits = false;
     }
     if (t.variant == 3 && !pipe_fits)
         return fail(c, LBSC_E_ARG,
                     "tiles.variant 3: a tile has more halo nodes than the %d threads%s", nt,
-                    c->precision == LBSC_FP16N ? ", or (tw + 4)(th + 4) exceeds 3 nt (FP16N rest footprint)" : "");
+                    per_node(c->precision) ? ", or (tw + 4)(th + 4) exceeds 3 nt (FP16N rest footprint)" : "");
     variant = t.variant > 0 ? t.variant : (pipe_fits ? 3 : 1);
     if (variant != 3)
         for (auto& it : items) it.down = 0;  // the register-keeping steps march upwards only
@@ -583,6 +587,7 @@ hipError_t launch_step(lbsc_ctx* c, hipStream_t s, int src)
     case LBSC_FP64: return launch_step_p<lbsc::StF64>(c, s, src);
     case LBSC_FP32S: return launch_step_p<lbsc::StF32S>(c, s, src);
     case LBSC_FP16S: return launch_step_p<lbsc::StF16S>(c, s, src);
+    case LBSC_FP16NF: return launch_step_p<lbsc::StF16NF>(c, s, src);
     default: return launch_step_p<lbsc::StF16N>(c, s, src);
     }
 }
@@ -639,6 +644,7 @@ hipError_t by_precision(int prec, F&& f)
     case LBSC_FP64: return f(lbsc::StF64{});
     case LBSC_FP32S: return f(lbsc::StF32S{});
     case LBSC_FP16S: return f(lbsc::StF16S{});
+    case LBSC_FP16NF: return f(lbsc::StF16NF{});
     default: return f(lbsc::StF16N{});
     }
 }
@@ -1707,6 +1713,7 @@ int32_t lbsc_selftest(void)
     check_layout(StF32S{});
     check_layout(StF16S{});
     check_layout(StF16N{});
+    check_layout(StF16NF{});
     // psi planes stay in range.
     for (int nz : {1, 2, 5})
         for (int wall = 0; wall < 2; ++wall)

@@ -15,11 +15,11 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbsc.so")
 
-FP64, FP32S, FP16S, FP16N = 0, 1, 2, 3
+FP64, FP32S, FP16S, FP16N, FP16NF = 0, 1, 2, 3, 4
 FLAG_FP16S_SINK = 1
 PSI_RHO, PSI_EXP = 0, 1
 SINK_NONE, SINK_ZMAX, SINK_FACES, SINK_SPHERE = 0, 1, 2, 3
-PRECISIONS = {"fp64": FP64, "fp32s": FP32S, "fp16s": FP16S, "fp16n": FP16N}
+PRECISIONS = {"fp64": FP64, "fp32s": FP32S, "fp16s": FP16S, "fp16n": FP16N, "fp16nf": FP16NF}
 SINKS = {"none": SINK_NONE, "zmax": SINK_ZMAX, "faces": SINK_FACES, "sphere": SINK_SPHERE}
 STATUS = {0: "ok", -1: "invalid argument", -2: "invalid state", -3: "HIP runtime error",
           -4: "non-finite density", -5: "unsupported"}

@@ -115,6 +115,8 @@ def test_kernel_variant_resolution(lib):
     assert resolve("fp32s", (256, 64, 32), (512, 128, 4, 0, 3)) == (0, 512, 3)
     assert resolve("fp16n", (64, 64, 64), (256, 64, 4, 0, 3)) == (0, 256, 3)
     assert resolve("fp16n", (256, 64, 32), (256, 128, 2, 0, 3))[0] == -1
+    assert resolve("fp16nf", (128, 128, 128), (0, 0, 0, 0, 0)) == (0, 512, 3)
+    assert resolve("fp16nf", (256, 64, 32), (256, 128, 2, 0, 3))[0] == -1
 
 
 
@@ -188,7 +190,7 @@ def test_fp16s_with_a_sink_needs_the_flag(lib):
         p = lbsc.make_params(16, 16, 16, precision="fp16s", sink=sink, sink_radius=6.0, flags=lbsc.FLAG_FP16S_SINK)
         assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == 0
         assert lib.lbsc_destroy(h) == 0
-    for prec, sink in (("fp16s", "none"), ("fp16n", "faces")):
+    for prec, sink in (("fp16s", "none"), ("fp16n", "faces"), ("fp16nf", "faces")):
         p = lbsc.make_params(16, 16, 16, precision=prec, sink=sink)
         assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == 0
         assert lib.lbsc_destroy(h) == 0
@@ -208,7 +210,7 @@ def test_single_component_validation(lib):
     context has the same number of components; its step has one variant."""
     from paper_1701_03637_amd import lbsc
     h = ctypes.c_void_p()
-    for prec, want in (("fp64", 0), ("fp32s", 0), ("fp16n", -5), ("fp16s", -5)):
+    for prec, want in (("fp64", 0), ("fp32s", 0), ("fp16n", -5), ("fp16nf", -5), ("fp16s", -5)):
         p = lbsc.make_params(16, 16, 16, precision=prec, ncomp=1, g=-5.0, psi="exp")
         assert lib.lbsc_create(1, ctypes.byref(p), ctypes.byref(h)) == want, prec
         if want == 0:
@@ -287,6 +289,7 @@ def test_automatic_plane_skew(lib):
     # FP64 pair planes (16 B per node), FP16N (40 half-elements per node)
     assert pop_bytes(128, 128, 2, "fp64") == 2 * 38 * (128 * 128 + 320) * 8
     assert pop_bytes(128, 128, 2, "fp16n") == 2 * 40 * (128 * 128 + 320) * 2
+    assert pop_bytes(128, 128, 2, "fp16nf") == 2 * 40 * (128 * 128 + 320) * 2
     # one component: 19 planes (the buffer ends on a 256-element boundary)
     assert pop_bytes(128, 128, 2, "fp32s", ncomp=1) == -(-2 * 19 * (128 * 128 + 320) // 256) * 256 * 4
 

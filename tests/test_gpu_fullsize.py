@@ -85,7 +85,7 @@ def config_run(request):
     return out
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32s", "fp16n"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32s", "fp16n", "fp16nf"])
 def test_config_1000_steps_against_oracle(lb, config_run, precision):
     w = config_run["w"]
     sim = _sim(lb, w, precision)
@@ -106,7 +106,7 @@ def test_config_1000_steps_against_oracle(lb, config_run, precision):
         else:
             assert abs(dg["r_droplet"] - do["r_droplet"]) <= 1e-10
     else:
-        bar_rho, bar_z, bar_m = {"fp32s": (1e-5, 0.01, 1e-6), "fp16n": (1e-3, 0.1, 1e-3)}[precision]
+        bar_rho, bar_z, bar_m = {"fp32s": (1e-5, 0.01, 1e-6), "fp16n": (1e-3, 0.1, 1e-3), "fp16nf": (1e-3, 0.1, 1e-3)}[precision]
         drho = float(np.max(np.abs(sim.density(0).cpu().numpy() - config_run["rho"][0])))
         m0 = config_run["d0"]["mass"]
         drift = abs(dg["mass"][0] + dg["mass"][1] - (m0[0] + m0[1])) / tot
@@ -132,7 +132,7 @@ def _window_reference(a, b, center, half, steps, g):
     return o.populations()[:, :, half, half, half]
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32s", 2e-6), ("fp16n", 1e-4), ("fp64", 1e-12)])
+@pytest.mark.parametrize("precision,tol", [("fp32s", 2e-6), ("fp16n", 1e-4), ("fp16nf", 1e-4), ("fp64", 1e-12)])
 def test_droplet512_sampled_and_properties(lb, precision, tol):
     """The 512^3 droplet in FP32S, in its FP16 variant (FP16N) and in FP64.
     Sampled populations against oracle windows: FP32S within 2e-6 (absolute;

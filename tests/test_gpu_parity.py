@@ -209,7 +209,7 @@ def test_fp64_droplet_ragged_tiles_and_sink_switch(lb):
 @pytest.mark.parametrize("tiles", [(256, 0, 0, 0, 1), (512, 0, 0, 0, 1), (256, 16, 4, 3, 1), (512, 32, 8, 7, 1),
                                    (256, 64, 2, 5, 1), (256, 0, 0, 0, 2), (512, 32, 8, 7, 2), (256, 64, 2, 5, 2),
                                    (256, 70, 3, 4, 1), (512, 256, 2, 6, 2)])
-@pytest.mark.parametrize("precision", ["fp64", "fp32s", "fp16s", "fp16n"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32s", "fp16s", "fp16n", "fp16nf"])
 def test_tile_schedules_bitwise_identical(lb, tiles, precision):
     """The result does not depend on the tile schedule (catches LDS halo races,
     ragged-tile indexing, and inlined copies of a store that round
@@ -256,7 +256,7 @@ PIPE_CASES = [
 
 
 @pytest.mark.parametrize("case", PIPE_CASES)
-@pytest.mark.parametrize("precision", ["fp32s", "fp16s", "fp64", "fp16n"])
+@pytest.mark.parametrize("precision", ["fp32s", "fp16s", "fp64", "fp16n", "fp16nf"])
 def test_pipelined_variant_bitwise_identical(lb, case, precision):
     """The pipelined step (one plane of loads ahead, four psi slots, halo
     wrapped inside tiles that span x or y, chunks marching up and down; FP16N
@@ -267,7 +267,7 @@ def test_pipelined_variant_bitwise_identical(lb, case, precision):
     tau = case[4] if len(case) > 4 else (1.0, 1.0)
     if precision == "fp64" and tiles[0] != 256:
         pytest.skip("the FP64 pipelined step runs 256-thread blocks")
-    if precision == "fp16n" and tiles[1] > 0 and (tiles[1] + 4) * (tiles[2] + 4) > 3 * tiles[0]:
+    if precision in ("fp16n", "fp16nf") and tiles[1] > 0 and (tiles[1] + 4) * (tiles[2] + 4) > 3 * tiles[0]:
         pytest.skip("the FP16N rest footprint (tw + 4)(th + 4) exceeds 3 nt")
     f0 = li.random_populations(nx, ny, nz, seed=5, base_a=0.3, base_b=0.4, amp=0.05)
 
@@ -331,7 +331,7 @@ def test_graph_replay_and_checkpoint_bitwise(lb):
     assert abs(dr["evaporated"] - dref["evaporated"]) < 1e-12
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32s", "fp16n"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32s", "fp16n", "fp16nf"])
 def test_every_graph_replay_matches_eager_steps(lb, precision):
     """Each replay of the step graph gives the bits of the same steps launched
     one by one. Eager work (diagnostics, with their synchronisation, and one
@@ -360,7 +360,7 @@ def test_every_graph_replay_matches_eager_steps(lb, precision):
             ref.step(1)
 
 
-@pytest.mark.parametrize("precision,tol_rho", [("fp32s", 1e-5), ("fp16n", 2e-4),
+@pytest.mark.parametrize("precision,tol_rho", [("fp32s", 1e-5), ("fp16n", 2e-4), ("fp16nf", 2e-4),
                                                pytest.param("fp16s", 1e-3, marks=pytest.mark.xfail(
                                                    reason="constant-shift FP16 quantises the slow dense-phase "
                                                           "dynamics of this sharp film; FP16N fixes it", strict=True))])
@@ -382,11 +382,14 @@ def test_reduced_precision_film_against_oracle(lb, precision, tol_rho):
     tot = do["mass"][0] + do["mass"][1]
     drift = abs(dg["mass"][0] + dg["mass"][1] - tot) / tot
     print(f"{precision}: total-mass drift {drift:.3e}")
-    assert drift < {"fp32s": 1e-6, "fp16n": 1e-6}.get(precision, 1e-3), drift
+    # FP16NF keeps deviations finer than FP32 resolves next to the dense
+    # phase's k_i d_0, so its decode drops parts its rest has counted: its
+    # drift (1.3e-6 measured) is about twice FP16N's (0.8e-6)
+    assert drift < {"fp32s": 1e-6, "fp16n": 1e-6, "fp16nf": 2e-6}.get(precision, 1e-3), drift
     assert abs(dg["z_interface"] - do["z_interface"]) < (0.01 if precision == "fp32s" else 0.1)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32s", 2e-6), ("fp16s", 2e-3), ("fp16n", 2e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp32s", 2e-6), ("fp16s", 2e-3), ("fp16n", 2e-5), ("fp16nf", 2e-5)])
 def test_reduced_precision_droplet_against_oracle(lb, precision, tol):
     nx = ny = nz = 40
     sim, orc = _pair(lb, nx, ny, nz, precision=precision, g=0.9, sink="faces", rho_h=0.04)
@@ -440,7 +443,7 @@ def test_nonfinite_density_is_reported(lb):
     step as NaN arithmetic (nothing faults) and the diagnostics return
     LBSC_E_NONFINITE with the count of affected nodes."""
     nx, ny, nz = 10, 9, 8
-    for precision in ("fp64", "fp32s", "fp16n"):
+    for precision in ("fp64", "fp32s", "fp16n", "fp16nf"):
         sim = lb.Sim(lb.make_params(nx, ny, nz, g=0.9, sink="faces", rho_h=0.03, precision=precision))
         a, b = li.droplet(nx, ny, nz, 2.5)
         a[4, 4, 5] = np.nan
@@ -579,11 +582,12 @@ SOLID_CASES = [
 
 # populations relative to max|f|, densities absolute, masses and E relative
 # to the total mass
-SOLID_BARS = {"fp64": (1e-12, 1e-12, 1e-13), "fp32s": (2e-6, 1e-5, 1e-6), "fp16n": (1e-3, 1e-3, 1e-4)}
+SOLID_BARS = {"fp64": (1e-12, 1e-12, 1e-13), "fp32s": (2e-6, 1e-5, 1e-6), "fp16n": (1e-3, 1e-3, 1e-4),
+              "fp16nf": (1e-3, 1e-3, 1e-4)}
 
 
 @pytest.mark.parametrize("case", SOLID_CASES)
-@pytest.mark.parametrize("precision", ["fp64", "fp32s", "fp16n"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32s", "fp16n", "fp16nf"])
 def test_solid_wall_matches_oracle(lb, case, precision):
     """Solid walls (Sec. III A, III B): a layer of solid planes below the
     fluid, half-way bounce-back on every link into it (also across the
@@ -647,7 +651,7 @@ def test_solid_wall_film_interface_matches_oracle(lb, precision):
     assert abs(dg["evaporated"] - do["evaporated"]) <= bar_e * tot
 
 
-@pytest.mark.parametrize("precision", ["fp32s", "fp16n", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32s", "fp16n", "fp16nf", "fp64"])
 def test_solid_wall_variants_bitwise(lb, precision):
     """The pipelined and register-keeping steps give the same bits above a
     solid wall, in chunks that reach the wall from both sides."""
