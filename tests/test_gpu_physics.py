@@ -382,12 +382,12 @@ def _vapour_diffusion(lb, ma, mb, nz=64, amp=1e-4, every=200):
     return -np.polyfit(ts[2:], np.log(amps[2:]), 1)[0] / (2 * np.pi / nz) ** 2
 
 
-@pytest.mark.parametrize("precision", ["fp32s", "fp16n"])
+@pytest.mark.parametrize("precision", ["fp32s", "fp16n", "fp16nf"])
 def test_droplet_128_follows_the_radius_laws(lb, surface_tension, precision):
     """Sec. III C at half the paper's scale: a droplet of R0 = 32 in 128^3
     with a spherical sink at R_H = 63, rho_H = 0.02, equilibrated 8000 steps,
     then evaporating until R < 10 (the paper fits diameters above 20), in
-    FP32S and in the FP16 form for long runs (FP16N).
+    FP32S and in the per-node FP16 forms (FP16N, FP16NF).
 
     D is measured from a composition wave at the mean vapour composition
     (the small-gradient formula of Eq. (diffu-t-1) overstates it there).
